@@ -85,3 +85,57 @@ def test_exact_ties_broken_by_lower_ids():
     assert got == want
     # ids: module0 -> 0,1 ; module1 -> 2,3 ; module2 -> 4 ; module3 -> 5
     assert got == [(5, 4, 2, 0)]
+
+
+def _event_from_modules(pts, mz):
+    xs, ys, zs, counts = [], [], [], []
+    for k in range(len(mz)):
+        counts.append(len(pts.get(k, [])))
+        for (a, b) in pts.get(k, []):
+            xs.append(a); ys.append(b); zs.append(mz[k])
+    mo = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+    return (np.array(xs, np.float32), np.array(ys, np.float32), np.array(zs, np.float32), mo,
+            np.asarray(mz, np.float32))
+
+
+def test_seed_tie_breaks_on_first_hit_then_third():
+    """Mirror-image doublets give two exactly-zero scatters, (a, d) and
+    (b, c) with a < b and c < d: the seed is the lexicographic minimum of
+    (scatter, id of first hit, id of third hit), i.e. (a, d)."""
+    mz = [0.0, 40.0, 80.0]
+    # reverse traversal: first module is index 2, middle 1, third 0
+    # module 0 (third): c=(10,+0.5) id 0, d=(10,-0.5) id 1
+    # module 1 (middle): (10, 0) id 2
+    # module 2 (first): a=(10,+0.5) id 3, b=(10,-0.5) id 4
+    ev = _event_from_modules({0: [(10.0, 0.5), (10.0, -0.5)], 1: [(10.0, 0.0)],
+                              2: [(10.0, 0.5), (10.0, -0.5)]}, mz)
+    p = dict(oracle.DEFAULTS)
+    got, want = _run_both(ev, p)
+    assert got == want == [(3, 2, 1)]
+
+
+def _straight_event(mz, x0, y0, tx, ty, zv=0.0):
+    pts = {k: [(x0 + tx * (z - zv), y0 + ty * (z - zv))] for k, z in enumerate(mz)}
+    return _event_from_modules(pts, mz)
+
+
+def test_thresholds_are_strict():
+    """A scatter or chi2 exactly equal to its threshold is rejected; the next
+    binary32 value above it accepts (strict '<' reading)."""
+    mz = [0.0, 40.0, 80.0]
+    x, y, z, mo, mzf = _event_from_modules({0: [(10.05, 0.1)], 1: [(10.0, 0.0)], 2: [(10.0, 0.0)]}, mz)
+    # reverse traversal: h0 = module 2 (id 2), h1 = module 1 (id 1), h2 = module 0 (id 0)
+    F = np.float32
+    d01 = F(z[1] - z[2]); tx = F(F(x[1] - x[2]) / d01); ty = F(F(y[1] - y[2]) / d01)
+    dz = F(z[0] - z[1]); dx = F(F(x[1] + F(tx * dz)) - x[0]); dy = F(F(y[1] + F(ty * dz)) - y[0])
+    sc = F(F(dx * dx) + F(dy * dy))
+    chi2 = F(oracle.tracklet_chi2(x[[2, 1, 0]], y[[2, 1, 0]], z[[2, 1, 0]]))
+    assert sc > 0 and chi2 > 0
+    up = lambda v: float(np.nextafter(F(v), F(np.inf)))
+    base = dict(oracle.DEFAULTS, max_tracklet_chi2=1.0)
+    ev = (x, y, z, mo, mzf)
+    assert _run_both(ev, dict(base, max_scatter_seeding=float(sc)))[0] == []
+    assert _run_both(ev, dict(base, max_scatter_seeding=up(sc)))[0] == [(2, 1, 0)]
+    base = dict(oracle.DEFAULTS, max_scatter_seeding=1.0)
+    assert _run_both(ev, dict(base, max_tracklet_chi2=float(chi2)))[0] == []
+    assert _run_both(ev, dict(base, max_tracklet_chi2=up(chi2)))[0] == [(2, 1, 0)]

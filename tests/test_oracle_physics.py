@@ -1,0 +1,136 @@
+"""End-to-end pins of the oracle: special cases with a known answer, the
+one-track-per-hit invariant, and the paper's quality indicators (Section 1)
+on generated straight tracks."""
+
+import numpy as np
+import pytest
+
+import oracle
+from _util import event_batch, tracks_per_event
+from paper_2207_03936_amd import indicators, synth
+
+
+def _line_event(present, x0=3.0, y0=-2.0, tx=0.021, ty=-0.013, noise=()):
+    """One noiseless straight track (sigma = 0) on the planes where
+    present[k] is true, plus optional extra hits (k, x, y)."""
+    mz = synth.PLANE_Z.astype(np.float32)
+    M = mz.size
+    per = [[] for _ in range(M)]
+    for k in range(M):
+        if present[k]:
+            per[k].append((np.float32(x0 + tx * mz[k]), np.float32(y0 + ty * mz[k])))
+    for (k, a, b) in noise:
+        per[k].append((np.float32(a), np.float32(b)))
+    xs, ys, zs, cnt = [], [], [], []
+    for k in range(M):
+        cnt.append(len(per[k]))
+        for a, b in per[k]:
+            xs.append(a); ys.append(b); zs.append(mz[k])
+    mo = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32)
+    return event_batch(np.array(xs, np.float32), np.array(ys, np.float32), np.array(zs, np.float32), mo, mz)
+
+
+def _modules_of(b, track):
+    mo = b.module_offsets
+    return [int(np.searchsorted(mo, h, side="right") - 1) for h in track]
+
+
+def test_single_track_all_planes():
+    b = _line_event(np.ones(26, bool))
+    (tracks,) = tracks_per_event(*oracle.reconstruct(b))
+    assert len(tracks) == 1
+    # all 26 hits, in traversal order (plane 25 first)
+    assert _modules_of(b, tracks[0]) == list(range(25, -1, -1))
+
+
+def test_single_missing_hit_does_not_split():
+    present = np.ones(26, bool)
+    present[12] = False
+    b = _line_event(present)
+    (tracks,) = tracks_per_event(*oracle.reconstruct(b))
+    assert len(tracks) == 1 and len(tracks[0]) == 25
+
+
+def test_two_consecutive_missing_hits_split():
+    present = np.ones(26, bool)
+    present[[12, 13]] = False
+    b = _line_event(present)
+    (tracks,) = tracks_per_event(*oracle.reconstruct(b))
+    assert sorted(len(t) for t in tracks) == [12, 12]
+    mods = sorted(_modules_of(b, t) for t in tracks)
+    assert mods == [list(range(11, -1, -1)), list(range(25, 13, -1))]
+
+
+def test_exactly_three_hits_is_an_accepted_tracklet():
+    present = np.zeros(26, bool)
+    present[[20, 21, 22]] = True
+    b = _line_event(present)
+    (tracks,) = tracks_per_event(*oracle.reconstruct(b))
+    assert [_modules_of(b, t) for t in tracks] == [[22, 21, 20]]
+
+
+def test_two_hit_and_empty_events_give_nothing():
+    present = np.zeros(26, bool)
+    present[[3, 4]] = True
+    assert tracks_per_event(*oracle.reconstruct(_line_event(present))) == [[]]
+    assert tracks_per_event(*oracle.reconstruct(_line_event(np.zeros(26, bool)))) == [[]]
+
+
+def test_forward_traversal_gives_the_same_track_reversed():
+    b = _line_event(np.ones(26, bool))
+    (fw,) = tracks_per_event(*oracle.reconstruct(b, reverse=0))
+    (bw,) = tracks_per_event(*oracle.reconstruct(b, reverse=1))
+    assert len(fw) == len(bw) == 1 and fw[0] == tuple(reversed(bw[0]))
+
+
+def check_invariants(b, out, X=oracle.DEFAULTS["max_tracklet_chi2"], misses=1, reverse=True):
+    eto, tho, th = out
+    M = b.n_modules
+    assert eto[0] == 0 and np.all(np.diff(eto) >= 0)
+    assert tho[0] == 0 and np.all(np.diff(tho) >= 3)
+    for e, tracks in enumerate(tracks_per_event(*out)):
+        lo, hi = int(b.event_offsets[e]), int(b.event_offsets[e + 1])
+        mo = b.module_offsets[e * M:(e + 1) * M + 1] - lo
+        used = np.concatenate([np.array(t) for t in tracks]) if tracks else np.zeros(0, int)
+        assert used.size == np.unique(used).size, "a hit belongs to two tracks"
+        assert np.all((used >= 0) & (used < hi - lo))
+        for t in tracks:
+            mods = np.searchsorted(mo, np.array(t), side="right") - 1
+            steps = -np.diff(mods) if reverse else np.diff(mods)
+            assert np.all(steps >= 1) and np.all(steps <= misses + 1)
+            if len(t) == 3:
+                hs = np.array(t) + lo
+                assert oracle.tracklet_chi2(b.x[hs], b.y[hs], b.z[hs]) < X
+
+
+@pytest.mark.parametrize("config,n", [("tiny", 50), ("mu7.6", 5), ("mu30", 2)])
+def test_invariants(config, n):
+    b = synth.make_batch(config, n)
+    check_invariants(b, oracle.reconstruct(b))
+
+
+def test_indicators_tiny():
+    """One vertex, 40 straight tracks, 99 % hit efficiency, 1 % noise."""
+    b = synth.make_batch("tiny", 100)
+    r = indicators.evaluate(b, *oracle.reconstruct(b))
+    assert r["efficiency"] >= 0.98
+    assert r["fake_fraction"] <= 0.01
+    assert r["clone_fraction"] <= 0.02
+    assert r["hit_purity"] >= 0.99
+    assert r["hit_efficiency"] >= 0.95
+
+
+def test_indicators_high_occupancy():
+    b = synth.make_batch("mu30", 3)
+    r = indicators.evaluate(b, *oracle.reconstruct(b))
+    assert r["efficiency"] >= 0.97
+    assert r["fake_fraction"] <= 0.02
+    assert r["hit_purity"] >= 0.98
+
+
+def test_golden_tracks_unchanged():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "tiny_event0_tracks.txt")
+    want = [tuple(int(v) for v in line.split()) for line in open(path) if not line.startswith("#")]
+    (got,) = tracks_per_event(*oracle.reconstruct(synth.make_batch("tiny", 1)))
+    assert got == want
