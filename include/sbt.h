@@ -1,0 +1,296 @@
+/*
+ * sbt.h -- C ABI of the MI355X (gfx950) Search by triplet library.
+ *
+ * Search by triplet reconstructs straight tracks in a vertex detector made of
+ * planes ("modules") perpendicular to the beam axis (paper, Section 1: the
+ * problem is to partition the hits into disjoint sets compatible with straight
+ * trajectories, allowing for noise; Section 3: the method).  One call
+ * reconstructs a batch of independent events (Section 3, "levels of
+ * parallelism": events are independent tasks).  Per event the library runs:
+ *
+ *   1. Sort by phi: a 16-bit angle per hit and the hits of every module
+ *      ordered by (phi16, hit id).
+ *   2. Track seeding and track following, alternating over consecutive
+ *      modules: seeds are the best-scatter triplet per unflagged middle hit
+ *      (pendulum search for doublet partners, phi window on the extrapolation
+ *      into the third module); following extends forming tracks by the
+ *      best-scatter hit of the next module and flags the hits it takes; a
+ *      forming track ends after two consecutive misses or at the last module.
+ *   3. Tracklet filter: three-hit tracks are kept only if a straight-line
+ *      least-squares fit is under a threshold and none of their hits is
+ *      flagged.
+ *   4. Output compaction into CSR arrays.
+ *
+ * Precise readings of the points the paper leaves open (tie-breaks, flag
+ * semantics, conflicting claims, thresholds) are given with each parameter
+ * below; every stage is deterministic, so the track set of an event does not
+ * depend on the batch, the launch configuration or the run.
+ *
+ * Conventions for every entry point
+ *   - Pointers inside sbt_hits / sbt_tracks are DEVICE pointers, owned by the
+ *     caller; the library neither frees them nor keeps them after the call
+ *     (except that a context's graph cache remembers their values).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  GPU entry points are
+ *     asynchronous: they only enqueue work; outputs are valid once the stream
+ *     has reached that point.  They return an error code for invalid host-side
+ *     arguments or a failed HIP call; per-event problems found on the device
+ *     are reported in sbt_tracks.event_status.
+ *   - Hit coordinates are binary32 millimetres.  Hits of an event are stored
+ *     contiguously and grouped by module index; a hit's event-local id is its
+ *     position inside its event.  Events hold at most 65,535 hits (hit ids
+ *     are 16-bit internally).
+ *   - Arithmetic is binary32, round to nearest even, no fused multiply-add
+ *     contraction, correctly rounded division, denormals kept.
+ */
+#ifndef SBT_H
+#define SBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBT_MAX_MODULES 64
+#define SBT_MAX_EVENT_HITS 65535
+
+/* return codes */
+#define SBT_OK 0
+#define SBT_ERR_INVALID_ARG (-1)     /* null pointer, parameter out of range          */
+#define SBT_ERR_EVENT_TOO_LARGE (-2) /* host-checked event above 65,535 hits          */
+#define SBT_ERR_HIP (-3)             /* a HIP runtime call failed                      */
+#define SBT_ERR_WORKSPACE (-4)       /* workspace or context capacity too small        */
+#define SBT_ERR_NOMEM (-5)           /* device or host allocation failed              */
+#define SBT_ERR_NOT_READY (-6)       /* serving: nothing to return yet / queue full    */
+
+/* event_status bits (0 = reconstructed) */
+#define SBT_EV_TOO_LARGE 1u   /* more than 65,535 hits: no tracks written           */
+#define SBT_EV_BAD_OFFSETS 2u /* offsets inconsistent or out of range: no tracks    */
+#define SBT_EV_INTERNAL 4u    /* internal consistency check failed (never expected) */
+
+/* Physics and geometry parameters.  They change results; the oracle takes the
+ * same values.  Defaults used by the tests and benchmark are in parentheses.
+ *
+ * n_modules       M, 3..64.  module_z[k] is the nominal z of module k; the phi
+ *                 window of an extrapolation is centred on the extrapolated
+ *                 position at this z (Section 3, seeding: "each doublet is
+ *                 extrapolated to the third module").
+ * reverse         1: traverse modules from index M-1 down to 0, i.e. starting
+ *                 furthest from the interaction region when z grows with the
+ *                 index; 0: from 0 up to M-1 (Section 3: the traversal
+ *                 direction is configurable).  (1)
+ * max_doublet_candidates
+ *                 K, unflagged partners collected by the pendulum search
+ *                 (Section 3: "until a threshold number of candidate hits that
+ *                 are not flagged is found"; its figure uses four).  >= 1.  (4)
+ * phi_window_seeding / phi_window_forwarding
+ *                 inclusive half-width W of the phi window, in phi16 units
+ *                 (2^16 per turn), 0..32767.  A hit is in the window of centre
+ *                 c iff its signed 16-bit difference to c is within [-W, W];
+ *                 the window wraps around the circle.  (416, 416)
+ * max_scatter_seeding / max_scatter_forwarding
+ *                 strict upper bound on the scatter dx^2 + dy^2 (mm^2)
+ *                 between a linear extrapolation and a candidate hit, both at
+ *                 the candidate's z (Section 3).  (0.04, 0.04)
+ * max_tracklet_chi2
+ *                 strict upper bound (mm^2) on the sum of squared residuals of
+ *                 least-squares lines x(z), y(z) through a three-hit track
+ *                 (Section 3, "Tracklet filter").  (0.002)
+ * max_consecutive_misses
+ *                 modules a forming track may skip in a row and still be
+ *                 followed (Section 3: "allowed for tracks to miss a
+ *                 module").  >= 0.  (1)
+ */
+typedef struct sbt_params {
+    int32_t n_modules;
+    float module_z[SBT_MAX_MODULES];
+    int32_t reverse;
+    int32_t max_doublet_candidates;
+    int32_t phi_window_seeding;
+    int32_t phi_window_forwarding;
+    float max_scatter_seeding;
+    float max_scatter_forwarding;
+    float max_tracklet_chi2;
+    int32_t max_consecutive_misses;
+} sbt_params;
+
+/* Input batch (device pointers).
+ * event_offsets   [n_events+1], event_offsets[0] = 0, non-decreasing,
+ *                 event_offsets[n_events] = n_hits.
+ * module_offsets  [n_events*M + 1] absolute hit offsets: module k of event e
+ *                 is [module_offsets[e*M+k], module_offsets[e*M+k+1]);
+ *                 module_offsets[e*M] = event_offsets[e].
+ * x, y, z         [n_hits] structure of arrays.                          */
+typedef struct sbt_hits {
+    int32_t n_events;
+    int32_t n_hits;
+    const int32_t *event_offsets;
+    const int32_t *module_offsets;
+    const float *x;
+    const float *y;
+    const float *z;
+} sbt_hits;
+
+/* Output (device pointers), CSR over events and tracks.  Capacities follow
+ * from the method: tracks are disjoint and have >= 3 hits.
+ * event_track_offsets [n_events+1]: tracks of event e are
+ *                 [event_track_offsets[e], event_track_offsets[e+1]).
+ * track_hit_offsets   [n_hits/3 + 1]: hits of track t are
+ *                 track_hits[track_hit_offsets[t] .. track_hit_offsets[t+1]).
+ * track_hits      [n_hits]: event-local hit ids in traversal order.
+ * event_status    [n_events] or NULL: SBT_EV_* bits, 0 when reconstructed.
+ * Tracks of an event are ordered by the id of their seed's middle hit.    */
+typedef struct sbt_tracks {
+    int32_t *event_track_offsets;
+    int32_t *track_hit_offsets;
+    int32_t *track_hits;
+    int32_t *event_status;
+} sbt_tracks;
+
+/* Launch configuration of the batched path.  It never changes results.
+ * threads_per_event   64, 128, 256 or 512 lanes cooperating on one event.
+ * blocks_per_cu       persistent workgroups per compute unit (1..16).
+ * lds_window_hits     capacity, in hits, of each LDS-staged module window;
+ *                     larger modules are read from global memory (0 = the
+ *                     library's default).                                  */
+typedef struct sbt_tuning {
+    int32_t threads_per_event;
+    int32_t blocks_per_cu;
+    int32_t lds_window_hits;
+    int32_t reserved;
+} sbt_tuning;
+
+/* Message for a return code (static storage). */
+const char *sbt_error_string(int code);
+
+/* Check a parameter block (host memory).  SBT_OK or SBT_ERR_INVALID_ARG. */
+int sbt_params_validate(const sbt_params *params);
+
+/* Host-side check of offsets held in HOST memory (optional; the device
+ * checks the same conditions per event and reports them in event_status).
+ * Returns SBT_OK, SBT_ERR_INVALID_ARG or SBT_ERR_EVENT_TOO_LARGE.         */
+int sbt_validate_offsets_host(int32_t n_modules, int32_t n_events, int32_t n_hits,
+                              const int32_t *event_offsets, const int32_t *module_offsets);
+
+/* ---- plain per-event form --------------------------------------------------
+ * Bytes of device workspace sbt_reconstruct needs for a batch of this size. */
+int sbt_workspace_size(int32_t n_events, int32_t n_hits, size_t *bytes);
+
+/* Reconstruct a batch with the plain per-event kernels: one workgroup per
+ * event and one launch per stage (phi sort, seeding and following, tracklet
+ * filter, per-event compaction, scan over events, CSR write), all enqueued on
+ * `stream`.  `workspace` is caller-owned device memory of at least
+ * sbt_workspace_size() bytes, 256-byte aligned; it must not be used by
+ * another call until this one has completed on the stream.               */
+int sbt_reconstruct(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- batched form ------------------------------------------------------------
+ * A context owns device workspace for up to max_events events / max_hits
+ * hits, the launch configuration and a cache of captured HIP graphs (one per
+ * distinct argument set).  Create and destroy on the host thread that uses it;
+ * a context runs one batch at a time (calls on different streams serialise on
+ * its workspace only if the caller orders them).                         */
+typedef struct sbt_context sbt_context;
+
+/* tuning NULL selects the library default for the current device. */
+int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning,
+                       int32_t max_events, int32_t max_hits, sbt_context **out);
+void sbt_context_destroy(sbt_context *ctx);
+int sbt_context_set_tuning(sbt_context *ctx, const sbt_tuning *tuning);
+int sbt_context_get_tuning(const sbt_context *ctx, sbt_tuning *out);
+
+/* Reconstruct a batch with the persistent work-stealing kernel: every stage
+ * of an event runs inside one workgroup, which then takes the next event
+ * from a device counter; the counter reset, the persistent kernel, the scan
+ * over events and the CSR write are replayed as one captured HIP graph.
+ * Same outputs as sbt_reconstruct, byte for byte.                        */
+int sbt_reconstruct_batched(sbt_context *ctx, const sbt_hits *hits, sbt_tracks *tracks,
+                            void *stream);
+
+/* Time the candidate launch configurations on `sample` (reps launches each,
+ * after one warm-up) and install the fastest in the context.  `tracks` is
+ * scratch output of the sample's size.  Writes the chosen tuning and its mean
+ * milliseconds per launch.  Synchronises `stream`.                        */
+int sbt_autotune(sbt_context *ctx, const sbt_hits *sample, sbt_tracks *tracks, void *stream,
+                 int32_t reps, sbt_tuning *best, float *best_ms);
+
+/* Stage timing of the last call on this context, in milliseconds, measured
+ * with HIP events on the call's stream when profiling is on (graphs are then
+ * bypassed).  stage_ms[0] = persistent kernel, [1] = scan, [2] = CSR write.
+ * Synchronises on the events.                                             */
+int sbt_context_set_profiling(sbt_context *ctx, int32_t on);
+int sbt_context_stage_ms(sbt_context *ctx, float *stage_ms, int32_t n);
+
+/* ---- inspection ----------------------------------------------------------------
+ * Run only the phi sort of the plain form and copy its result: for every
+ * hit position p of the batch (module by module, phi16 ascending, ties by
+ * lower id) phi_sorted[p] is the 16-bit angle and ids_sorted[p] the
+ * event-local id.  Device pointers of n_hits uint16 each.                */
+int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted,
+                       uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
+                       void *stream);
+
+/* ---- serving ---------------------------------------------------------------------
+ * Continuous batching of single events that arrive over time.  The server
+ * keeps `n_slots` batches of device memory resident (inputs, workspace and
+ * outputs, `slot_hits`/`slot_events` capacity each, all inside
+ * `device_budget_bytes`), admits queued events into the open slot while it
+ * has room, and launches a slot on its own stream as soon as its previous
+ * launch is complete and either it is full or `max_wait_us` passed since its
+ * oldest event was queued.  Several slots are in flight at once, so events
+ * that arrive while others are on the GPU overlap with them.  Results of an
+ * event are identical to reconstructing it alone.                        */
+typedef struct sbt_server sbt_server;
+
+typedef struct sbt_server_config {
+    size_t device_budget_bytes;  /* upper bound on the server's device memory    */
+    int32_t n_slots;             /* resident batches (>= 1)                        */
+    int32_t slot_events;         /* events per batch (>= 1)                        */
+    int32_t slot_hits;           /* hits per batch (>= 65,535 so any event fits)   */
+    int32_t max_wait_us;         /* launch a partial batch after this wait         */
+} sbt_server_config;
+
+/* A completed event: its tracks in the same CSR form as one event of
+ * sbt_tracks (offsets local to this event), valid until the next
+ * sbt_server_poll call on this server.                                    */
+typedef struct sbt_server_result {
+    int64_t request_id;
+    int32_t status;              /* event_status bits                             */
+    int32_t n_tracks;
+    const int32_t *track_hit_offsets;  /* host, [n_tracks+1]                    */
+    const int32_t *track_hits;         /* host                                   */
+    double t_submit_us;          /* host clock (microseconds, monotonic)           */
+    double t_done_us;            /* when the result was visible on the host        */
+} sbt_server_result;
+
+int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning,
+                      const sbt_server_config *config, sbt_server **out);
+void sbt_server_destroy(sbt_server *srv);
+
+/* Queue one event from HOST memory (copied before return).  module_offsets
+ * has n_modules+1 event-local entries.  Returns SBT_OK, SBT_ERR_INVALID_ARG,
+ * SBT_ERR_EVENT_TOO_LARGE, or SBT_ERR_NOT_READY when the host queue holds
+ * max queued events (n_slots * slot_events * 4).                          */
+int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits,
+                      const int32_t *module_offsets, const float *x, const float *y,
+                      const float *z);
+
+/* Drive the server: admit, launch and collect.  Writes up to max_results
+ * completed events; returns their number (>= 0) or an error.  With
+ * wait_us > 0 it blocks up to that long for at least one completion.      */
+int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_results,
+                    int32_t wait_us);
+
+/* Events queued on the host, and events on the device. */
+int sbt_server_pending(const sbt_server *srv, int32_t *queued, int32_t *in_flight);
+
+/* Host monotonic clock in microseconds (the clock of t_submit_us). */
+double sbt_now_us(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBT_H */

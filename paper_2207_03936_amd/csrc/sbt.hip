@@ -1,0 +1,716 @@
+// Search by triplet for MI355X (gfx950): kernels and the C ABI of include/sbt.h.
+//
+// Plain form: one workgroup per event and one launch per stage.
+// Batched form: a persistent work-stealing kernel that runs every stage of an
+// event inside one workgroup and then takes the next event from a device
+// counter, followed by a scan over events and the CSR write, replayed as one
+// captured HIP graph.  Both forms share the device stages of sbt_device.h and
+// give byte-identical outputs.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "sbt.h"
+#include "sbt_device.h"
+#include "sbt_internal.h"
+
+using namespace sbt;
+
+// ============================================================== kernels
+
+// plain form ----------------------------------------------------------------
+
+template <int B>
+__global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W)
+{
+    __shared__ Shared<B> S;
+    const int e = blockIdx.x;
+    int hb, N;
+    const int st = load_event<B>(P, H, e, S, &hb, &N);
+    if (threadIdx.x == 0) W.ev_st[e] = st;
+    if (st != 0) return;
+    stage_sort<B>(P, H, W, hb, N, S);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W)
+{
+    __shared__ Shared<B> S;
+    const int e = blockIdx.x;
+    if (W.ev_st[e] != 0) return;
+    int hb, N;
+    load_event<B>(P, H, e, S, &hb, &N);
+    stage_track<B>(P, H, W, hb, N, S);
+    if (threadIdx.x == 0) W.ev_nfin[e] = S.cnt[3];
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_weak_filter(sbt_params P, HitsArgs H, Work W)
+{
+    const int e = blockIdx.x;
+    if (W.ev_st[e] != 0) return;
+    const int hb = H.eo[e];
+    stage_filter<B>(P, W, hb, W.ev_nfin[e]);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
+{
+    __shared__ int scan[B / 64 + 1];
+    const int e = blockIdx.x;
+    if (W.ev_st[e] != 0) {
+        if (threadIdx.x == 0) { W.ev_nt[e] = 0; W.ev_nh[e] = 0; }
+        return;
+    }
+    const int hb = H.eo[e];
+    stage_compact<B>(W, e, hb, H.eo[e + 1] - hb, scan);
+}
+
+// batched form ----------------------------------------------------------------
+
+__global__ void k_reset_counter(unsigned int *counter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W)
+{
+    __shared__ Shared<B> S;
+    for (;;) {
+        if (threadIdx.x == 0) S.e = (int)atomicAdd(W.counter, 1u);
+        __syncthreads();
+        const int e = S.e;
+        if (e >= H.n_events) break;
+        int hb, N;
+        const int st = load_event<B>(P, H, e, S, &hb, &N);
+        if (threadIdx.x == 0) W.ev_st[e] = st;
+        if (st == 0) {
+            stage_sort<B>(P, H, W, hb, N, S);
+            stage_track<B>(P, H, W, hb, N, S);
+            stage_filter<B>(P, W, hb, S.cnt[3]);
+            stage_compact<B>(W, e, hb, N, S.scan);
+        } else if (threadIdx.x == 0) {
+            W.ev_nt[e] = 0;
+            W.ev_nh[e] = 0;
+        }
+        __syncthreads();
+    }
+}
+
+// shared tail -----------------------------------------------------------------
+
+// exclusive scan over events of the per-event track and hit counts
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutArgs O)
+{
+    const int E = H.n_events;
+    __shared__ int sw[kScanThreads / 64 + 1];
+    const int chunk = (E + kScanThreads - 1) / kScanThreads;
+    const int beg = threadIdx.x * chunk;
+    const int end = min(beg + chunk, E);
+    int st = 0, sh = 0;
+    for (int i = beg; i < end; ++i) {
+        st += W.ev_nt[i];
+        sh += W.ev_nh[i];
+    }
+    int tt, th;
+    int ot = block_excl_scan<kScanThreads>(st, sw, &tt);
+    int oh = block_excl_scan<kScanThreads>(sh, sw, &th);
+    for (int i = beg; i < end; ++i) {
+        O.eto[i] = ot;
+        W.ev_hb[i] = oh;
+        ot += W.ev_nt[i];
+        oh += W.ev_nh[i];
+    }
+    if (threadIdx.x == 0) {
+        O.eto[E] = tt;
+        if (tt <= H.n_hits / 3) O.tho[tt] = th;
+    }
+}
+
+constexpr int kWriteThreads = 256;
+__global__ __launch_bounds__(kWriteThreads) void k_write(HitsArgs H, Work W, OutArgs O)
+{
+    for (int e = blockIdx.x; e < H.n_events; e += gridDim.x) {
+        if (O.status && threadIdx.x == 0) O.status[e] = W.ev_st[e];
+        const int nt = W.ev_nt[e], nh = W.ev_nh[e];
+        if (nt == 0) continue;
+        const int hb = H.eo[e];
+        const int t0 = O.eto[e], p0 = W.ev_hb[e];
+        for (int i = threadIdx.x; i < nt; i += kWriteThreads) O.tho[t0 + i] = p0 + W.st_toff[hb + i];
+        for (int j = threadIdx.x; j < nh; j += kWriteThreads) O.th[p0 + j] = W.st_hits[hb + j];
+    }
+}
+
+// debug: copy the sorted phi16 and ids
+__global__ void k_copy_sorted(int H, Work W, uint16_t *phi, uint16_t *ids)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x) {
+        phi[i] = W.sq[i];
+        ids[i] = W.sid[i];
+    }
+}
+
+// ============================================================== host side
+
+namespace {
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Carves the workspace; with base == nullptr only the size is computed.
+size_t carve(int32_t E, int32_t H, char *base, Work *W)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes ? bytes : 1);
+        return p;
+    };
+    const size_t h = (size_t)(H > 0 ? H : 1);
+    const size_t e = (size_t)(E > 0 ? E : 1);
+    Work w;
+    w.q = (uint16_t *)take(2 * h);
+    w.bucket = (uint16_t *)take(2 * h);
+    w.sx = (float *)take(4 * h);
+    w.sy = (float *)take(4 * h);
+    w.sz = (float *)take(4 * h);
+    w.sq = (uint16_t *)take(2 * h);
+    w.sid = (uint16_t *)take(2 * h);
+    w.owner = (uint16_t *)take(2 * h);
+    w.claim = (unsigned long long *)take(8 * h);
+    w.prev = (uint16_t *)take(2 * h);
+    w.rec = (Rec *)take(sizeof(Rec) * h);
+    w.rbest = (uint16_t *)take(2 * h);
+    w.rbsc = (float *)take(4 * h);
+    w.rchi2 = (float *)take(4 * h);
+    w.rflag = (uint8_t *)take(h);
+    w.act0 = (uint16_t *)take(2 * h);
+    w.act1 = (uint16_t *)take(2 * h);
+    w.fin = (uint16_t *)take(2 * h);
+    w.key2rec = (uint16_t *)take(2 * h);
+    w.st_hits = (uint16_t *)take(2 * h);
+    w.st_toff = (int32_t *)take(4 * h);
+    w.ev_nt = (int32_t *)take(4 * e);
+    w.ev_nh = (int32_t *)take(4 * e);
+    w.ev_hb = (int32_t *)take(4 * e);
+    w.ev_st = (int32_t *)take(4 * e);
+    w.ev_nfin = (int32_t *)take(4 * e);
+    w.counter = (unsigned int *)take(256);
+    if (W) *W = w;
+    return off;
+}
+
+bool is_pow_tpe(int v) { return v == 64 || v == 128 || v == 256 || v == 512; }
+
+int check_hits(const sbt_hits *h)
+{
+    if (!h) return SBT_ERR_INVALID_ARG;
+    if (h->n_events < 0 || h->n_hits < 0) return SBT_ERR_INVALID_ARG;
+    if (h->n_events > 0 && (!h->event_offsets || !h->module_offsets)) return SBT_ERR_INVALID_ARG;
+    if (h->n_hits > 0 && (!h->x || !h->y || !h->z)) return SBT_ERR_INVALID_ARG;
+    return SBT_OK;
+}
+
+int check_tracks(const sbt_tracks *t)
+{
+    if (!t || !t->event_track_offsets || !t->track_hit_offsets || !t->track_hits) return SBT_ERR_INVALID_ARG;
+    return SBT_OK;
+}
+
+HitsArgs hits_args(const sbt_hits *h)
+{
+    HitsArgs a;
+    a.n_events = h->n_events;
+    a.n_hits = h->n_hits;
+    a.eo = h->event_offsets;
+    a.mo = h->module_offsets;
+    a.x = h->x;
+    a.y = h->y;
+    a.z = h->z;
+    return a;
+}
+
+OutArgs out_args(const sbt_tracks *t)
+{
+    OutArgs o;
+    o.eto = t->event_track_offsets;
+    o.tho = t->track_hit_offsets;
+    o.th = t->track_hits;
+    o.status = t->event_status;
+    return o;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        if ((expr) != hipSuccess) return SBT_ERR_HIP;   \
+    } while (0)
+
+constexpr int kPlainThreads = 256;
+
+int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hipStream_t s)
+{
+    const dim3 g(H.n_events), b(kPlainThreads);
+    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, 0, s, P, H, W);
+    hipLaunchKernelGGL(k_seed_follow<kPlainThreads>, g, b, 0, s, P, H, W);
+    hipLaunchKernelGGL(k_weak_filter<kPlainThreads>, g, b, 0, s, P, H, W);
+    hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, 0, s, H, W);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+int launch_tail(const HitsArgs &H, const Work &W, const OutArgs &O, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, H, W, O);
+    const int grid = std::min(H.n_events, 8192);
+    if (grid > 0) hipLaunchKernelGGL(k_write, dim3(grid), dim3(kWriteThreads), 0, s, H, W, O);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+typedef void (*persistent_fn)(sbt_params, HitsArgs, Work);
+
+persistent_fn persistent_kernel(int tpe)
+{
+    switch (tpe) {
+    case 64: return k_persistent<64>;
+    case 128: return k_persistent<128>;
+    case 256: return k_persistent<256>;
+    case 512: return k_persistent<512>;
+    default: return nullptr;
+    }
+}
+
+int device_cus(int *cus)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return SBT_OK;
+}
+
+int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
+{
+    int cus = 0;
+    int rc = device_cus(&cus);
+    if (rc) return rc;
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, reinterpret_cast<const void *>(persistent_kernel(T.threads_per_event)), T.threads_per_event, 0));
+    int bpc = std::max(1, std::min(T.blocks_per_cu, std::max(occ, 1)));
+    *grid = std::max(1, std::min(cus * bpc, std::max(n_events, 1)));
+    return SBT_OK;
+}
+
+int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W,
+                   const OutArgs &O, hipStream_t s, hipEvent_t *marks)
+{
+    int grid = 0;
+    int rc = persistent_grid(T, H.n_events, &grid);
+    if (rc) return rc;
+    if (marks) HIP_TRY(hipEventRecord(marks[0], s));
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, W.counter);
+    hipLaunchKernelGGL(persistent_kernel(T.threads_per_event), dim3(grid), dim3(T.threads_per_event), 0, s,
+                       P, H, W);
+    if (marks) HIP_TRY(hipEventRecord(marks[1], s));
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, H, W, O);
+    if (marks) HIP_TRY(hipEventRecord(marks[2], s));
+    const int wg = std::min(H.n_events, 8192);
+    if (wg > 0) hipLaunchKernelGGL(k_write, dim3(wg), dim3(kWriteThreads), 0, s, H, W, O);
+    if (marks) HIP_TRY(hipEventRecord(marks[3], s));
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+// write an empty result (no events) without launching kernels that need any
+__global__ void k_empty(OutArgs O)
+{
+    if (threadIdx.x == 0) {
+        O.eto[0] = 0;
+        O.tho[0] = 0;
+    }
+}
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char *sbt_error_string(int code)
+{
+    switch (code) {
+    case SBT_OK: return "ok";
+    case SBT_ERR_INVALID_ARG: return "invalid argument";
+    case SBT_ERR_EVENT_TOO_LARGE: return "event has more than 65535 hits";
+    case SBT_ERR_HIP: return "HIP runtime error";
+    case SBT_ERR_WORKSPACE: return "workspace or context too small";
+    case SBT_ERR_NOMEM: return "allocation failed";
+    case SBT_ERR_NOT_READY: return "not ready";
+    default: return "unknown error";
+    }
+}
+
+int sbt_params_validate(const sbt_params *p)
+{
+    if (!p) return SBT_ERR_INVALID_ARG;
+    if (p->n_modules < 3 || p->n_modules > SBT_MAX_MODULES) return SBT_ERR_INVALID_ARG;
+    if (p->max_doublet_candidates < 1) return SBT_ERR_INVALID_ARG;
+    if (p->phi_window_seeding < 0 || p->phi_window_seeding > 32767) return SBT_ERR_INVALID_ARG;
+    if (p->phi_window_forwarding < 0 || p->phi_window_forwarding > 32767) return SBT_ERR_INVALID_ARG;
+    if (p->max_consecutive_misses < 0) return SBT_ERR_INVALID_ARG;
+    if (p->reverse != 0 && p->reverse != 1) return SBT_ERR_INVALID_ARG;
+    // nominal z strictly monotone in the module index
+    bool inc = true, dec = true;
+    for (int k = 1; k < p->n_modules; ++k) {
+        if (!(p->module_z[k] > p->module_z[k - 1])) inc = false;
+        if (!(p->module_z[k] < p->module_z[k - 1])) dec = false;
+    }
+    if (!inc && !dec) return SBT_ERR_INVALID_ARG;
+    return SBT_OK;
+}
+
+int sbt_validate_offsets_host(int32_t M, int32_t E, int32_t H, const int32_t *eo, const int32_t *mo)
+{
+    if (M < 3 || M > SBT_MAX_MODULES || E < 0 || H < 0) return SBT_ERR_INVALID_ARG;
+    if (E > 0 && (!eo || !mo)) return SBT_ERR_INVALID_ARG;
+    if (E == 0) return SBT_OK;
+    if (eo[0] != 0 || eo[E] != H) return SBT_ERR_INVALID_ARG;
+    int too_large = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        if (eo[e + 1] < eo[e]) return SBT_ERR_INVALID_ARG;
+        if (eo[e + 1] - eo[e] > SBT_MAX_EVENT_HITS) too_large = 1;
+        const int64_t b = (int64_t)e * M;
+        if (mo[b] != eo[e] || mo[b + M] != eo[e + 1]) return SBT_ERR_INVALID_ARG;
+        for (int k = 0; k < M; ++k)
+            if (mo[b + k + 1] < mo[b + k]) return SBT_ERR_INVALID_ARG;
+    }
+    return too_large ? SBT_ERR_EVENT_TOO_LARGE : SBT_OK;
+}
+
+int sbt_workspace_size(int32_t n_events, int32_t n_hits, size_t *bytes)
+{
+    if (!bytes || n_events < 0 || n_hits < 0) return SBT_ERR_INVALID_ARG;
+    *bytes = carve(n_events, n_hits, nullptr, nullptr);
+    return SBT_OK;
+}
+
+int sbt_reconstruct(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks, void *workspace,
+                    size_t workspace_bytes, void *stream)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const HitsArgs H = hits_args(hits);
+    const OutArgs O = out_args(tracks);
+    if (H.n_events == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
+        return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255)) return SBT_ERR_INVALID_ARG;
+    if (workspace_bytes < carve(H.n_events, H.n_hits, nullptr, nullptr)) return SBT_ERR_WORKSPACE;
+    Work W;
+    carve(H.n_events, H.n_hits, (char *)workspace, &W);
+    if ((rc = launch_plain_front(*params, H, W, s))) return rc;
+    return launch_tail(H, W, O, s);
+}
+
+int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted, uint16_t *ids_sorted,
+                       void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if ((rc = check_hits(hits))) return rc;
+    if (!phi_sorted || !ids_sorted) return SBT_ERR_INVALID_ARG;
+    if (hits->n_events == 0 || hits->n_hits == 0) return SBT_OK;
+    if (!workspace || ((uintptr_t)workspace & 255)) return SBT_ERR_INVALID_ARG;
+    if (workspace_bytes < carve(hits->n_events, hits->n_hits, nullptr, nullptr)) return SBT_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Work W;
+    carve(hits->n_events, hits->n_hits, (char *)workspace, &W);
+    const HitsArgs H = hits_args(hits);
+    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, dim3(H.n_events), dim3(kPlainThreads), 0, s, *params, H, W);
+    hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
+                       phi_sorted, ids_sorted);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+}  // extern "C"
+
+// ============================================================== context
+
+struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+
+struct sbt_context {
+    sbt_params params;
+    sbt_tuning tuning;
+    int32_t max_events;
+    int32_t max_hits;
+    void *workspace;
+    size_t workspace_bytes;
+    Work W;
+    std::vector<GraphEntry> graphs;
+    uint64_t clock;
+    int profiling;
+    hipEvent_t marks[4];
+    int have_marks;
+};
+
+namespace {
+
+constexpr size_t kMaxGraphs = 8;
+
+void drop_graphs(sbt_context *c)
+{
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+int valid_tuning(const sbt_tuning &t)
+{
+    if (!is_pow_tpe(t.threads_per_event)) return SBT_ERR_INVALID_ARG;
+    if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return SBT_ERR_INVALID_ARG;
+    if (t.lds_window_hits < 0) return SBT_ERR_INVALID_ARG;
+    return SBT_OK;
+}
+
+sbt_tuning default_tuning()
+{
+    sbt_tuning t;
+    t.threads_per_event = 256;
+    t.blocks_per_cu = 4;
+    t.lds_window_hits = 0;
+    t.reserved = 0;
+    return t;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning, int32_t max_events, int32_t max_hits,
+                       sbt_context **out)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if (!out || max_events < 0 || max_hits < 0) return SBT_ERR_INVALID_ARG;
+    sbt_tuning t = tuning ? *tuning : default_tuning();
+    if ((rc = valid_tuning(t))) return rc;
+    sbt_context *c = new (std::nothrow) sbt_context();
+    if (!c) return SBT_ERR_NOMEM;
+    c->params = *params;
+    c->tuning = t;
+    c->max_events = max_events;
+    c->max_hits = max_hits;
+    c->workspace_bytes = carve(max_events, max_hits, nullptr, nullptr);
+    c->clock = 0;
+    c->profiling = 0;
+    c->have_marks = 0;
+    if (hipMalloc(&c->workspace, c->workspace_bytes) != hipSuccess) {
+        delete c;
+        return SBT_ERR_NOMEM;
+    }
+    carve(max_events, max_hits, (char *)c->workspace, &c->W);
+    for (int i = 0; i < 4; ++i) {
+        if (hipEventCreate(&c->marks[i]) != hipSuccess) {
+            for (int j = 0; j < i; ++j) (void)hipEventDestroy(c->marks[j]);
+            (void)hipFree(c->workspace);
+            delete c;
+            return SBT_ERR_HIP;
+        }
+    }
+    *out = c;
+    return SBT_OK;
+}
+
+void sbt_context_destroy(sbt_context *c)
+{
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    drop_graphs(c);
+    for (int i = 0; i < 4; ++i) (void)hipEventDestroy(c->marks[i]);
+    (void)hipFree(c->workspace);
+    delete c;
+}
+
+int sbt_context_set_tuning(sbt_context *c, const sbt_tuning *t)
+{
+    if (!c || !t) return SBT_ERR_INVALID_ARG;
+    int rc = valid_tuning(*t);
+    if (rc) return rc;
+    if (memcmp(&c->tuning, t, sizeof *t) != 0) {
+        c->tuning = *t;
+        drop_graphs(c);
+    }
+    return SBT_OK;
+}
+
+int sbt_context_get_tuning(const sbt_context *c, sbt_tuning *out)
+{
+    if (!c || !out) return SBT_ERR_INVALID_ARG;
+    *out = c->tuning;
+    return SBT_OK;
+}
+
+int sbt_context_set_profiling(sbt_context *c, int32_t on)
+{
+    if (!c) return SBT_ERR_INVALID_ARG;
+    c->profiling = on ? 1 : 0;
+    return SBT_OK;
+}
+
+int sbt_context_stage_ms(sbt_context *c, float *ms, int32_t n)
+{
+    if (!c || !ms || n < 1) return SBT_ERR_INVALID_ARG;
+    if (!c->have_marks) return SBT_ERR_NOT_READY;
+    HIP_TRY(hipEventSynchronize(c->marks[3]));
+    for (int i = 0; i < n && i < 3; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], c->marks[i], c->marks[i + 1]));
+    return SBT_OK;
+}
+
+int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tracks, void *stream)
+{
+    if (!c) return SBT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
+    if (hits->n_events > c->max_events || hits->n_hits > c->max_hits) return SBT_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const HitsArgs H = hits_args(hits);
+    const OutArgs O = out_args(tracks);
+    if (H.n_events == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
+        return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+    }
+    if (c->profiling || s == nullptr) {
+        rc = launch_batched(c->params, c->tuning, H, c->W, O, s, c->profiling ? c->marks : nullptr);
+        if (rc == SBT_OK && c->profiling) c->have_marks = 1;
+        return rc;
+    }
+    std::vector<uintptr_t> key = {
+        (uintptr_t)H.n_events, (uintptr_t)H.n_hits, (uintptr_t)H.eo, (uintptr_t)H.mo, (uintptr_t)H.x,
+        (uintptr_t)H.y, (uintptr_t)H.z, (uintptr_t)O.eto, (uintptr_t)O.tho, (uintptr_t)O.th, (uintptr_t)O.status};
+    ++c->clock;
+    for (auto &g : c->graphs) {
+        if (g.key == key) {
+            g.last_use = c->clock;
+            HIP_TRY(hipGraphLaunch(g.exec, s));
+            return SBT_OK;
+        }
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = launch_batched(c->params, c->tuning, H, c->W, O, s, nullptr);
+    hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (rc != SBT_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc ? rc : SBT_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    ec = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ec != hipSuccess) return SBT_ERR_HIP;
+    if (c->graphs.size() >= kMaxGraphs) {
+        auto victim = std::min_element(c->graphs.begin(), c->graphs.end(),
+                                       [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
+        (void)hipGraphExecDestroy(victim->exec);
+        c->graphs.erase(victim);
+    }
+    c->graphs.push_back(GraphEntry{key, exec, c->clock});
+    HIP_TRY(hipGraphLaunch(exec, s));
+    return SBT_OK;
+}
+
+int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, void *stream, int32_t reps,
+                 sbt_tuning *best, float *best_ms)
+{
+    if (!c || reps < 1) return SBT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_hits(sample)) || (rc = check_tracks(tracks))) return rc;
+    if (sample->n_events > c->max_events || sample->n_hits > c->max_hits) return SBT_ERR_WORKSPACE;
+    if (sample->n_events == 0) return SBT_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const HitsArgs H = hits_args(sample);
+    const OutArgs O = out_args(tracks);
+    hipEvent_t t0, t1;
+    HIP_TRY(hipEventCreate(&t0));
+    if (hipEventCreate(&t1) != hipSuccess) {
+        (void)hipEventDestroy(t0);
+        return SBT_ERR_HIP;
+    }
+    const int tpes[] = {64, 128, 256, 512};
+    const int bpcs[] = {1, 2, 4, 8, 16};
+    sbt_tuning win = c->tuning;
+    float win_ms = -1.0f;
+    rc = SBT_OK;
+    for (int tpe : tpes) {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(persistent_kernel(tpe)),
+                                                          tpe, 0) != hipSuccess) {
+            rc = SBT_ERR_HIP;
+            break;
+        }
+        for (int bpc : bpcs) {
+            if (bpc > std::max(occ, 1)) continue;
+            sbt_tuning t = c->tuning;
+            t.threads_per_event = tpe;
+            t.blocks_per_cu = bpc;
+            if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
+            if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
+            for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);
+            if (rc) break;
+            float ms = 0.0f;
+            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+                rc = SBT_ERR_HIP;
+                break;
+            }
+            ms /= (float)reps;
+            if (win_ms < 0.0f || ms < win_ms) {
+                win_ms = ms;
+                win = t;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc) return rc;
+    sbt_context_set_tuning(c, &win);
+    if (best) *best = win;
+    if (best_ms) *best_ms = win_ms;
+    return SBT_OK;
+}
+
+}  // extern "C"
+
+// ============================================================== internal API
+
+namespace sbt {
+
+size_t workspace_bytes(int32_t E, int32_t H) { return carve(E, H, nullptr, nullptr); }
+
+int launch_batched_raw(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
+                       const sbt_tracks &tracks, void *workspace, hipStream_t stream)
+{
+    const HitsArgs H = hits_args(&hits);
+    const OutArgs O = out_args(&tracks);
+    if (H.n_events == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, stream, O);
+        return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+    }
+    Work W;
+    carve(H.n_events, H.n_hits, (char *)workspace, &W);
+    return launch_batched(params, tuning, H, W, O, stream, nullptr);
+}
+
+sbt_tuning default_tuning_config() { return default_tuning(); }
+int tuning_valid(const sbt_tuning &t) { return valid_tuning(t); }
+
+}  // namespace sbt

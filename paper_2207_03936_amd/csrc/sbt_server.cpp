@@ -1,0 +1,414 @@
+// Serving loop: continuous batching of single events over resident device
+// slots (the C ABI in include/sbt.h, "serving").
+//
+// Each slot owns, for the server's lifetime, device inputs, workspace and
+// outputs for up to slot_events events / slot_hits hits, pinned host staging
+// for both directions, a stream (default priority) and a completion event.
+// Events queued by sbt_server_submit are packed into the slot that is open
+// for admission; a slot is launched (H2D copy, batched reconstruction, D2H
+// copy, completion event, all on its stream) when it cannot take the next
+// queued event, when its oldest event has waited max_wait_us, or at once when
+// no other slot is on the device.  While slots are in flight, newly arriving
+// events are admitted into free slots, so their work overlaps on the device.
+// An event's tracks depend only on its own hits, so a result is the same
+// whether the event ran alone or in a mix.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <chrono>
+#include <deque>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "sbt.h"
+#include "sbt_internal.h"
+
+namespace {
+
+double now_us()
+{
+    using namespace std::chrono;
+    return (double)duration_cast<nanoseconds>(steady_clock::now().time_since_epoch()).count() * 1e-3;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct QueuedEvent {
+    int64_t id;
+    double t_submit;
+    std::vector<int32_t> mo;   // M+1 local offsets
+    std::vector<float> xyz;    // x[n], y[n], z[n]
+    int32_t n;
+};
+
+struct SlotEvent {
+    int64_t id;
+    double t_submit;
+};
+
+enum SlotState { kFree = 0, kOpen = 1, kInFlight = 2 };
+
+struct Slot {
+    // device
+    char *dmem = nullptr;
+    float *dx = nullptr, *dy = nullptr, *dz = nullptr;
+    int32_t *deo = nullptr, *dmo = nullptr;
+    int32_t *deto = nullptr, *dtho = nullptr, *dth = nullptr, *dst = nullptr;
+    void *dwork = nullptr;
+    // pinned host, same layout as the device inputs / outputs
+    char *hin = nullptr;
+    float *hx = nullptr, *hy = nullptr, *hz = nullptr;
+    int32_t *heo = nullptr, *hmo = nullptr;
+    char *hout = nullptr;
+    int32_t *heto = nullptr, *htho = nullptr, *hth = nullptr, *hst = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    SlotState state = kFree;
+    int32_t n_events = 0, n_hits = 0;
+    double t_oldest = 0.0;
+    std::vector<SlotEvent> events;
+};
+
+struct ResultStore {
+    std::vector<int32_t> tho;
+    std::vector<int32_t> th;
+};
+
+}  // namespace
+
+struct sbt_server {
+    sbt_params params;
+    sbt_tuning tuning;
+    sbt_server_config cfg;
+    std::vector<Slot> slots;
+    std::deque<QueuedEvent> queue;
+    size_t max_queue;
+    int open_slot;           // index of the slot admitting events, or -1
+    std::vector<ResultStore> store;
+    std::deque<sbt_server_result> ready;   // completed, not yet returned
+    std::deque<ResultStore> ready_store;
+};
+
+namespace {
+
+// byte layout of one slot
+struct SlotLayout {
+    size_t x, y, z, eo, mo, in_total;      // inputs
+    size_t eto, tho, th, st, out_total;    // outputs
+    size_t work;
+    size_t device_total;
+};
+
+SlotLayout slot_layout(const sbt_server_config &c, int M)
+{
+    SlotLayout L;
+    const size_t H = (size_t)c.slot_hits, E = (size_t)c.slot_events;
+    size_t o = 0;
+    L.x = o; o += align_up(4 * H);
+    L.y = o; o += align_up(4 * H);
+    L.z = o; o += align_up(4 * H);
+    L.eo = o; o += align_up(4 * (E + 1));
+    L.mo = o; o += align_up(4 * (E * M + 1));
+    L.in_total = o;
+    size_t p = 0;
+    L.eto = p; p += align_up(4 * (E + 1));
+    L.tho = p; p += align_up(4 * (H / 3 + 1));
+    L.th = p; p += align_up(4 * H);
+    L.st = p; p += align_up(4 * E);
+    L.out_total = p;
+    L.work = align_up(sbt::workspace_bytes(c.slot_events, c.slot_hits));
+    L.device_total = L.in_total + L.out_total + L.work;
+    return L;
+}
+
+void free_slot(Slot &s)
+{
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.dmem) (void)hipFree(s.dmem);
+    if (s.hin) (void)hipHostFree(s.hin);
+    if (s.hout) (void)hipHostFree(s.hout);
+    s = Slot();
+}
+
+int init_slot(Slot &s, const SlotLayout &L)
+{
+    if (hipMalloc(&s.dmem, L.device_total) != hipSuccess) return SBT_ERR_NOMEM;
+    if (hipHostMalloc(&s.hin, L.in_total, hipHostMallocDefault) != hipSuccess) return SBT_ERR_NOMEM;
+    if (hipHostMalloc(&s.hout, L.out_total, hipHostMallocDefault) != hipSuccess) return SBT_ERR_NOMEM;
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return SBT_ERR_HIP;
+    if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return SBT_ERR_HIP;
+    char *d = s.dmem;
+    s.dx = (float *)(d + L.x);
+    s.dy = (float *)(d + L.y);
+    s.dz = (float *)(d + L.z);
+    s.deo = (int32_t *)(d + L.eo);
+    s.dmo = (int32_t *)(d + L.mo);
+    char *dout = d + L.in_total;
+    s.deto = (int32_t *)(dout + L.eto);
+    s.dtho = (int32_t *)(dout + L.tho);
+    s.dth = (int32_t *)(dout + L.th);
+    s.dst = (int32_t *)(dout + L.st);
+    s.dwork = d + L.in_total + L.out_total;
+    s.hx = (float *)(s.hin + L.x);
+    s.hy = (float *)(s.hin + L.y);
+    s.hz = (float *)(s.hin + L.z);
+    s.heo = (int32_t *)(s.hin + L.eo);
+    s.hmo = (int32_t *)(s.hin + L.mo);
+    s.heto = (int32_t *)(s.hout + L.eto);
+    s.htho = (int32_t *)(s.hout + L.tho);
+    s.hth = (int32_t *)(s.hout + L.th);
+    s.hst = (int32_t *)(s.hout + L.st);
+    s.state = kFree;
+    return SBT_OK;
+}
+
+// Packs a queued event into an open slot's pinned inputs.
+void pack(sbt_server *srv, Slot &s, const QueuedEvent &q)
+{
+    const int M = srv->params.n_modules;
+    if (s.n_events == 0) {
+        s.heo[0] = 0;
+        s.hmo[0] = 0;
+        s.t_oldest = q.t_submit;
+    }
+    const int32_t base = s.n_hits;
+    memcpy(s.hx + base, q.xyz.data(), sizeof(float) * q.n);
+    memcpy(s.hy + base, q.xyz.data() + q.n, sizeof(float) * q.n);
+    memcpy(s.hz + base, q.xyz.data() + 2 * (size_t)q.n, sizeof(float) * q.n);
+    for (int k = 1; k <= M; ++k) s.hmo[(size_t)s.n_events * M + k] = base + q.mo[k];
+    s.n_hits += q.n;
+    s.n_events += 1;
+    s.heo[s.n_events] = s.n_hits;
+    s.events.push_back(SlotEvent{q.id, q.t_submit});
+}
+
+int launch(sbt_server *srv, Slot &s)
+{
+    const int M = srv->params.n_modules;
+    const SlotLayout L = slot_layout(srv->cfg, M);
+    const size_t E = (size_t)s.n_events, H = (size_t)s.n_hits;
+    hipStream_t st = s.stream;
+    // inputs (only the used prefix of each array)
+    if (H > 0) {
+        if (hipMemcpyAsync(s.dx, s.hx, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+        if (hipMemcpyAsync(s.dy, s.hy, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+        if (hipMemcpyAsync(s.dz, s.hz, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+    }
+    if (hipMemcpyAsync(s.deo, s.heo, 4 * (E + 1), hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+    if (hipMemcpyAsync(s.dmo, s.hmo, 4 * (E * M + 1), hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+    sbt_hits hits;
+    hits.n_events = (int32_t)E;
+    hits.n_hits = (int32_t)H;
+    hits.event_offsets = s.deo;
+    hits.module_offsets = s.dmo;
+    hits.x = s.dx;
+    hits.y = s.dy;
+    hits.z = s.dz;
+    sbt_tracks tr;
+    tr.event_track_offsets = s.deto;
+    tr.track_hit_offsets = s.dtho;
+    tr.track_hits = s.dth;
+    tr.event_status = s.dst;
+    int rc = sbt::launch_batched_raw(srv->params, srv->tuning, hits, tr, s.dwork, st);
+    if (rc) return rc;
+    // outputs: capacities follow from the input size (tracks are disjoint, >= 3 hits)
+    if (hipMemcpyAsync(s.heto, s.deto, 4 * (E + 1), hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
+    if (hipMemcpyAsync(s.htho, s.dtho, 4 * (H / 3 + 1), hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
+    if (H > 0 && hipMemcpyAsync(s.hth, s.dth, 4 * H, hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
+    if (hipMemcpyAsync(s.hst, s.dst, 4 * E, hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
+    if (hipEventRecord(s.done, st) != hipSuccess) return SBT_ERR_HIP;
+    (void)L;
+    s.state = kInFlight;
+    return SBT_OK;
+}
+
+// Moves a completed slot's events to the ready queue.
+void collect(sbt_server *srv, Slot &s)
+{
+    const double t = now_us();
+    for (int32_t i = 0; i < s.n_events; ++i) {
+        const int32_t t0 = s.heto[i], t1 = s.heto[i + 1];
+        ResultStore rs;
+        rs.tho.resize((size_t)(t1 - t0) + 1);
+        const int32_t h0 = s.htho[t0];
+        for (int32_t k = t0; k <= t1; ++k) rs.tho[(size_t)(k - t0)] = s.htho[k] - h0;
+        rs.th.assign(s.hth + h0, s.hth + s.htho[t1]);
+        sbt_server_result r;
+        r.request_id = s.events[(size_t)i].id;
+        r.status = s.hst[i];
+        r.n_tracks = t1 - t0;
+        r.track_hit_offsets = nullptr;
+        r.track_hits = nullptr;
+        r.t_submit_us = s.events[(size_t)i].t_submit;
+        r.t_done_us = t;
+        srv->ready.push_back(r);
+        srv->ready_store.push_back(std::move(rs));
+    }
+    s.events.clear();
+    s.n_events = 0;
+    s.n_hits = 0;
+    s.state = kFree;
+}
+
+int step(sbt_server *srv)
+{
+    // 1. collect completed slots
+    int in_flight = 0;
+    for (auto &s : srv->slots) {
+        if (s.state != kInFlight) continue;
+        hipError_t q = hipEventQuery(s.done);
+        if (q == hipSuccess) collect(srv, s);
+        else if (q == hipErrorNotReady) ++in_flight;
+        else return SBT_ERR_HIP;
+    }
+    // 2. admit queued events into the open slot, opening free slots as needed
+    const double t = now_us();
+    while (!srv->queue.empty()) {
+        if (srv->open_slot < 0) {
+            for (size_t i = 0; i < srv->slots.size(); ++i)
+                if (srv->slots[i].state == kFree) {
+                    srv->open_slot = (int)i;
+                    srv->slots[i].state = kOpen;
+                    break;
+                }
+            if (srv->open_slot < 0) break;   // every slot is busy: events wait on the host
+        }
+        Slot &s = srv->slots[(size_t)srv->open_slot];
+        const QueuedEvent &q = srv->queue.front();
+        if (s.n_events + 1 > srv->cfg.slot_events || s.n_hits + q.n > srv->cfg.slot_hits) {
+            int rc = launch(srv, s);        // full: launch it and open another
+            if (rc) return rc;
+            ++in_flight;
+            srv->open_slot = -1;
+            continue;
+        }
+        pack(srv, s, q);
+        srv->queue.pop_front();
+    }
+    // 3. launch the open slot when it waited long enough or the device is idle
+    if (srv->open_slot >= 0) {
+        Slot &s = srv->slots[(size_t)srv->open_slot];
+        if (s.n_events > 0 && (in_flight == 0 || t - s.t_oldest >= (double)srv->cfg.max_wait_us)) {
+            int rc = launch(srv, s);
+            if (rc) return rc;
+            srv->open_slot = -1;
+        }
+    }
+    return SBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+double sbt_now_us(void) { return now_us(); }
+
+int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const sbt_server_config *config,
+                      sbt_server **out)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if (!config || !out) return SBT_ERR_INVALID_ARG;
+    const sbt_server_config &c = *config;
+    if (c.n_slots < 1 || c.slot_events < 1 || c.slot_hits < SBT_MAX_EVENT_HITS || c.max_wait_us < 0)
+        return SBT_ERR_INVALID_ARG;
+    sbt_tuning t = tuning ? *tuning : sbt::default_tuning_config();
+    if ((rc = sbt::tuning_valid(t))) return rc;
+    const SlotLayout L = slot_layout(c, params->n_modules);
+    if ((size_t)c.n_slots * L.device_total > c.device_budget_bytes) return SBT_ERR_WORKSPACE;
+    sbt_server *srv = new (std::nothrow) sbt_server();
+    if (!srv) return SBT_ERR_NOMEM;
+    srv->params = *params;
+    srv->tuning = t;
+    srv->cfg = c;
+    srv->max_queue = (size_t)c.n_slots * (size_t)c.slot_events * 4;
+    srv->open_slot = -1;
+    srv->slots.resize((size_t)c.n_slots);
+    for (auto &s : srv->slots) {
+        if ((rc = init_slot(s, L))) {
+            for (auto &x : srv->slots) free_slot(x);
+            delete srv;
+            return rc;
+        }
+    }
+    *out = srv;
+    return SBT_OK;
+}
+
+void sbt_server_destroy(sbt_server *srv)
+{
+    if (!srv) return;
+    for (auto &s : srv->slots)
+        if (s.stream) (void)hipStreamSynchronize(s.stream);
+    for (auto &s : srv->slots) free_slot(s);
+    delete srv;
+}
+
+int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits, const int32_t *module_offsets,
+                      const float *x, const float *y, const float *z)
+{
+    if (!srv || n_hits < 0 || !module_offsets) return SBT_ERR_INVALID_ARG;
+    if (n_hits > 0 && (!x || !y || !z)) return SBT_ERR_INVALID_ARG;
+    if (n_hits > SBT_MAX_EVENT_HITS) return SBT_ERR_EVENT_TOO_LARGE;
+    const int M = srv->params.n_modules;
+    if (module_offsets[0] != 0 || module_offsets[M] != n_hits) return SBT_ERR_INVALID_ARG;
+    for (int k = 0; k < M; ++k)
+        if (module_offsets[k + 1] < module_offsets[k]) return SBT_ERR_INVALID_ARG;
+    if (srv->queue.size() >= srv->max_queue) return SBT_ERR_NOT_READY;
+    QueuedEvent q;
+    q.id = request_id;
+    q.t_submit = now_us();
+    q.n = n_hits;
+    q.mo.assign(module_offsets, module_offsets + M + 1);
+    q.xyz.resize(3 * (size_t)n_hits);
+    if (n_hits > 0) {
+        memcpy(q.xyz.data(), x, sizeof(float) * n_hits);
+        memcpy(q.xyz.data() + n_hits, y, sizeof(float) * n_hits);
+        memcpy(q.xyz.data() + 2 * (size_t)n_hits, z, sizeof(float) * n_hits);
+    }
+    srv->queue.push_back(std::move(q));
+    return SBT_OK;
+}
+
+int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_results, int32_t wait_us)
+{
+    if (!srv || (max_results > 0 && !results) || max_results < 0) return SBT_ERR_INVALID_ARG;
+    srv->store.clear();
+    const double t_end = now_us() + (wait_us > 0 ? (double)wait_us : 0.0);
+    for (;;) {
+        int rc = step(srv);
+        if (rc) return rc;
+        if (!srv->ready.empty() || now_us() >= t_end) break;
+        std::this_thread::yield();
+    }
+    int32_t n = 0;
+    while (n < max_results && !srv->ready.empty()) {
+        srv->store.push_back(std::move(srv->ready_store.front()));
+        srv->ready_store.pop_front();
+        results[n] = srv->ready.front();
+        srv->ready.pop_front();
+        ++n;
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        results[i].track_hit_offsets = srv->store[(size_t)i].tho.data();
+        results[i].track_hits = srv->store[(size_t)i].th.data();
+    }
+    return n;
+}
+
+int sbt_server_pending(const sbt_server *srv, int32_t *queued, int32_t *in_flight)
+{
+    if (!srv) return SBT_ERR_INVALID_ARG;
+    int32_t q = (int32_t)srv->queue.size(), f = 0;
+    for (const auto &s : srv->slots)
+        if (s.state != kFree) f += s.n_events;
+    if (queued) *queued = q;
+    if (in_flight) *in_flight = f + (int32_t)srv->ready.size();
+    return SBT_OK;
+}
+
+}  // extern "C"

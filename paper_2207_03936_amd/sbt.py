@@ -1,0 +1,411 @@
+"""Python binding of ``libsbt.so`` (include/sbt.h): argument marshalling only.
+
+Every step of the reconstruction runs in the library's HIP kernels; this
+module fills the C structs, allocates device buffers with torch and passes
+torch's current stream.  It never computes tracks itself: if the library is
+not built, or no GPU is present, the calls raise.
+
+The functions carry the C names (``sbt_reconstruct``,
+``sbt_reconstruct_batched``, ``sbt_context_create`` ...).  ``DeviceBatch``
+and ``DeviceTracks`` hold the device buffers of one call.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsbt.so")
+
+MAX_MODULES = 64
+SBT_OK = 0
+SBT_ERR_INVALID_ARG = -1
+SBT_ERR_EVENT_TOO_LARGE = -2
+SBT_ERR_HIP = -3
+SBT_ERR_WORKSPACE = -4
+SBT_ERR_NOMEM = -5
+SBT_ERR_NOT_READY = -6
+SBT_EV_TOO_LARGE = 1
+SBT_EV_BAD_OFFSETS = 2
+
+DEFAULT_PARAMS = dict(
+    reverse=1,
+    max_doublet_candidates=4,
+    phi_window_seeding=416,
+    phi_window_forwarding=416,
+    max_scatter_seeding=0.04,
+    max_scatter_forwarding=0.04,
+    max_tracklet_chi2=0.002,
+    max_consecutive_misses=1,
+)
+
+
+class SbtParams(ctypes.Structure):
+    _fields_ = [("n_modules", ctypes.c_int32),
+                ("module_z", ctypes.c_float * MAX_MODULES),
+                ("reverse", ctypes.c_int32),
+                ("max_doublet_candidates", ctypes.c_int32),
+                ("phi_window_seeding", ctypes.c_int32),
+                ("phi_window_forwarding", ctypes.c_int32),
+                ("max_scatter_seeding", ctypes.c_float),
+                ("max_scatter_forwarding", ctypes.c_float),
+                ("max_tracklet_chi2", ctypes.c_float),
+                ("max_consecutive_misses", ctypes.c_int32)]
+
+
+class SbtHits(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int32), ("n_hits", ctypes.c_int32),
+                ("event_offsets", ctypes.c_void_p), ("module_offsets", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class SbtTracks(ctypes.Structure):
+    _fields_ = [("event_track_offsets", ctypes.c_void_p), ("track_hit_offsets", ctypes.c_void_p),
+                ("track_hits", ctypes.c_void_p), ("event_status", ctypes.c_void_p)]
+
+
+class SbtTuning(ctypes.Structure):
+    _fields_ = [("threads_per_event", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("lds_window_hits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(threads_per_event=self.threads_per_event, blocks_per_cu=self.blocks_per_cu,
+                    lds_window_hits=self.lds_window_hits)
+
+
+class SbtServerConfig(ctypes.Structure):
+    _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int32),
+                ("slot_events", ctypes.c_int32), ("slot_hits", ctypes.c_int32),
+                ("max_wait_us", ctypes.c_int32)]
+
+
+class SbtServerResult(ctypes.Structure):
+    _fields_ = [("request_id", ctypes.c_int64), ("status", ctypes.c_int32), ("n_tracks", ctypes.c_int32),
+                ("track_hit_offsets", ctypes.POINTER(ctypes.c_int32)),
+                ("track_hits", ctypes.POINTER(ctypes.c_int32)),
+                ("t_submit_us", ctypes.c_double), ("t_done_us", ctypes.c_double)]
+
+
+# exported symbols and their prototypes (restype, argtypes)
+_P = ctypes.POINTER
+_VP = ctypes.c_void_p
+PROTOTYPES = {
+    "sbt_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sbt_params_validate": (ctypes.c_int, [_P(SbtParams)]),
+    "sbt_validate_offsets_host": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                 _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "sbt_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_size_t)]),
+    "sbt_reconstruct": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _P(SbtTracks), _VP, ctypes.c_size_t, _VP]),
+    "sbt_context_create": (ctypes.c_int, [_P(SbtParams), _P(SbtTuning), ctypes.c_int32, ctypes.c_int32, _P(_VP)]),
+    "sbt_context_destroy": (None, [_VP]),
+    "sbt_context_set_tuning": (ctypes.c_int, [_VP, _P(SbtTuning)]),
+    "sbt_context_get_tuning": (ctypes.c_int, [_VP, _P(SbtTuning)]),
+    "sbt_reconstruct_batched": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP]),
+    "sbt_autotune": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP, ctypes.c_int32, _P(SbtTuning),
+                                    _P(ctypes.c_float)]),
+    "sbt_context_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "sbt_context_stage_ms": (ctypes.c_int, [_VP, _P(ctypes.c_float), ctypes.c_int32]),
+    "sbt_debug_phi_sort": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "sbt_server_create": (ctypes.c_int, [_P(SbtParams), _P(SbtTuning), _P(SbtServerConfig), _P(_VP)]),
+    "sbt_server_destroy": (None, [_VP]),
+    "sbt_server_submit": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_int32),
+                                         _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float)]),
+    "sbt_server_poll": (ctypes.c_int, [_VP, _P(SbtServerResult), ctypes.c_int32, ctypes.c_int32]),
+    "sbt_server_pending": (ctypes.c_int, [_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "sbt_now_us": (ctypes.c_double, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libsbt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2207_03936_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in PROTOTYPES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class SbtError(RuntimeError):
+    def __init__(self, code, what=""):
+        msg = lib().sbt_error_string(code).decode()
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+def _check(code, what=""):
+    if code != SBT_OK:
+        raise SbtError(code, what)
+    return code
+
+
+def make_params(module_z, **overrides) -> SbtParams:
+    p = dict(DEFAULT_PARAMS)
+    p.update(overrides)
+    module_z = np.asarray(module_z, dtype=np.float32)
+    sp = SbtParams()
+    sp.n_modules = int(module_z.size)
+    for k, v in enumerate(module_z):
+        sp.module_z[k] = float(v)
+    for key in DEFAULT_PARAMS:
+        setattr(sp, key, p[key])
+    return sp
+
+
+def make_tuning(threads_per_event=256, blocks_per_cu=4, lds_window_hits=0) -> SbtTuning:
+    t = SbtTuning()
+    t.threads_per_event = threads_per_event
+    t.blocks_per_cu = blocks_per_cu
+    t.lds_window_hits = lds_window_hits
+    t.reserved = 0
+    return t
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU available: the Search by triplet library runs only on the device")
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class DeviceBatch:
+    """Device copy of a packed batch (any object with x, y, z, event_offsets,
+    module_offsets): the sbt_hits of a call."""
+
+    def __init__(self, batch, device="cuda"):
+        torch = _torch()
+        self.n_events = int(batch.event_offsets.shape[0] - 1)
+        self.n_hits = int(batch.event_offsets[-1]) if self.n_events > 0 else 0
+        self.n_modules = int(batch.module_z.shape[0])
+        self.module_z = np.asarray(batch.module_z, dtype=np.float32)
+
+        def dev(a, dt):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=dt))
+            if t.numel() == 0:
+                t = torch.zeros(1, dtype=t.dtype)
+            return t.to(device)
+        self.x = dev(batch.x, np.float32)
+        self.y = dev(batch.y, np.float32)
+        self.z = dev(batch.z, np.float32)
+        self.eo = dev(batch.event_offsets, np.int32)
+        self.mo = dev(batch.module_offsets, np.int32)
+        self.hits = SbtHits(self.n_events, self.n_hits, self.eo.data_ptr(), self.mo.data_ptr(),
+                            self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr())
+
+
+class DeviceTracks:
+    """Output buffers sized for a batch: the sbt_tracks of a call."""
+
+    def __init__(self, n_events, n_hits, device="cuda"):
+        torch = _torch()
+        self.n_events, self.n_hits = int(n_events), int(n_hits)
+        self.eto = torch.zeros(self.n_events + 1, dtype=torch.int32, device=device)
+        self.tho = torch.zeros(self.n_hits // 3 + 1, dtype=torch.int32, device=device)
+        self.th = torch.zeros(max(self.n_hits, 1), dtype=torch.int32, device=device)
+        self.status = torch.zeros(max(self.n_events, 1), dtype=torch.int32, device=device)
+        self.tracks = SbtTracks(self.eto.data_ptr(), self.tho.data_ptr(), self.th.data_ptr(),
+                                self.status.data_ptr())
+
+    def fill_(self, value=-7):
+        for t in (self.eto, self.tho, self.th, self.status):
+            t.fill_(value)
+        return self
+
+    def to_host(self):
+        """(event_track_offsets, track_hit_offsets, track_hits, event_status),
+        trimmed, as int32 numpy arrays (synchronises)."""
+        eto = self.eto.cpu().numpy()
+        T = int(eto[-1])
+        tho = self.tho[:T + 1].cpu().numpy()
+        th = self.th[:int(tho[-1])].cpu().numpy()
+        return eto, tho, th, self.status[:self.n_events].cpu().numpy()
+
+
+# ------------------------------------------------------------------ plain form
+
+def sbt_workspace_size(n_events, n_hits) -> int:
+    n = ctypes.c_size_t(0)
+    _check(lib().sbt_workspace_size(int(n_events), int(n_hits), ctypes.byref(n)), "sbt_workspace_size")
+    return int(n.value)
+
+
+class Workspace:
+    def __init__(self, n_events, n_hits, device="cuda"):
+        torch = _torch()
+        self.bytes = sbt_workspace_size(n_events, n_hits)
+        self.buf = torch.empty(self.bytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        self.ptr = (base + 255) & ~255
+
+
+def sbt_reconstruct(params: SbtParams, batch: DeviceBatch, out: Optional[DeviceTracks] = None,
+                    workspace: Optional[Workspace] = None, stream=None) -> DeviceTracks:
+    """Plain per-event kernels (asynchronous on torch's current stream)."""
+    out = out or DeviceTracks(batch.n_events, batch.n_hits)
+    ws = workspace or Workspace(batch.n_events, batch.n_hits)
+    _check(lib().sbt_reconstruct(ctypes.byref(params), ctypes.byref(batch.hits), ctypes.byref(out.tracks),
+                                 ctypes.c_void_p(ws.ptr), ws.bytes, _stream_handle(stream)), "sbt_reconstruct")
+    out._keep = ws
+    return out
+
+
+def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None):
+    """(phi16, ids) of every hit position after the per-module phi sort."""
+    torch = _torch()
+    ws = Workspace(batch.n_events, batch.n_hits)
+    phi = torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda")
+    ids = torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda")
+    _check(lib().sbt_debug_phi_sort(ctypes.byref(params), ctypes.byref(batch.hits),
+                                    ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                                    ctypes.c_void_p(ws.ptr), ws.bytes, _stream_handle(stream)), "sbt_debug_phi_sort")
+    n = batch.n_hits
+    return (phi[:n].cpu().numpy().view(np.uint16), ids[:n].cpu().numpy().view(np.uint16))
+
+
+# ------------------------------------------------------------------ batched form
+
+class Context:
+    """sbt_context: workspace, launch configuration and graph cache."""
+
+    def __init__(self, params: SbtParams, max_events: int, max_hits: int, tuning: Optional[SbtTuning] = None):
+        _torch()
+        self.params = params
+        h = ctypes.c_void_p(0)
+        _check(lib().sbt_context_create(ctypes.byref(params), ctypes.byref(tuning) if tuning else None,
+                                        int(max_events), int(max_hits), ctypes.byref(h)), "sbt_context_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().sbt_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, tuning: SbtTuning):
+        _check(lib().sbt_context_set_tuning(self.handle, ctypes.byref(tuning)), "sbt_context_set_tuning")
+
+    def get_tuning(self) -> SbtTuning:
+        t = SbtTuning()
+        _check(lib().sbt_context_get_tuning(self.handle, ctypes.byref(t)), "sbt_context_get_tuning")
+        return t
+
+    def set_profiling(self, on: bool):
+        _check(lib().sbt_context_set_profiling(self.handle, 1 if on else 0), "sbt_context_set_profiling")
+
+    def stage_ms(self):
+        arr = (ctypes.c_float * 3)()
+        _check(lib().sbt_context_stage_ms(self.handle, arr, 3), "sbt_context_stage_ms")
+        return [float(v) for v in arr]
+
+    def reconstruct(self, batch: DeviceBatch, out: Optional[DeviceTracks] = None, stream=None) -> DeviceTracks:
+        out = out or DeviceTracks(batch.n_events, batch.n_hits)
+        _check(lib().sbt_reconstruct_batched(self.handle, ctypes.byref(batch.hits), ctypes.byref(out.tracks),
+                                             _stream_handle(stream)), "sbt_reconstruct_batched")
+        return out
+
+    def autotune(self, sample: DeviceBatch, reps: int = 3, stream=None):
+        out = DeviceTracks(sample.n_events, sample.n_hits)
+        best = SbtTuning()
+        ms = ctypes.c_float(0)
+        _check(lib().sbt_autotune(self.handle, ctypes.byref(sample.hits), ctypes.byref(out.tracks),
+                                  _stream_handle(stream), int(reps), ctypes.byref(best), ctypes.byref(ms)),
+               "sbt_autotune")
+        return best, float(ms.value)
+
+
+def sbt_context_create(params, max_events, max_hits, tuning=None) -> Context:
+    return Context(params, max_events, max_hits, tuning)
+
+
+def sbt_reconstruct_batched(ctx: Context, batch: DeviceBatch, out=None, stream=None) -> DeviceTracks:
+    return ctx.reconstruct(batch, out, stream)
+
+
+def sbt_autotune(ctx: Context, sample: DeviceBatch, reps=3, stream=None):
+    return ctx.autotune(sample, reps, stream)
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """sbt_server: continuous batching over resident device slots."""
+
+    def __init__(self, params: SbtParams, device_budget_bytes: int, n_slots: int = 4, slot_events: int = 256,
+                 slot_hits: int = 1 << 21, max_wait_us: int = 200, tuning: Optional[SbtTuning] = None):
+        _torch()
+        self.n_modules = params.n_modules
+        cfg = SbtServerConfig(int(device_budget_bytes), int(n_slots), int(slot_events), int(slot_hits),
+                              int(max_wait_us))
+        h = ctypes.c_void_p(0)
+        _check(lib().sbt_server_create(ctypes.byref(params), ctypes.byref(tuning) if tuning else None,
+                                       ctypes.byref(cfg), ctypes.byref(h)), "sbt_server_create")
+        self.handle = h
+        self._res = (SbtServerResult * 1024)()
+
+    def close(self):
+        if self.handle:
+            lib().sbt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, request_id, module_offsets, x, y, z) -> int:
+        mo = np.ascontiguousarray(module_offsets, dtype=np.int32)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        z = np.ascontiguousarray(z, dtype=np.float32)
+        f = ctypes.POINTER(ctypes.c_float)
+        return lib().sbt_server_submit(self.handle, int(request_id), int(x.size),
+                                       mo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       x.ctypes.data_as(f), y.ctypes.data_as(f), z.ctypes.data_as(f))
+
+    def poll(self, wait_us: int = 0):
+        """List of (request_id, status, track_hit_offsets, track_hits,
+        t_submit_us, t_done_us) for the events completed so far."""
+        n = lib().sbt_server_poll(self.handle, self._res, len(self._res), int(wait_us))
+        if n < 0:
+            raise SbtError(n, "sbt_server_poll")
+        out = []
+        for i in range(n):
+            r = self._res[i]
+            nt = r.n_tracks
+            tho = np.ctypeslib.as_array(r.track_hit_offsets, shape=(nt + 1,)).copy()
+            th = (np.ctypeslib.as_array(r.track_hits, shape=(int(tho[-1]),)).copy()
+                  if tho[-1] > 0 else np.zeros(0, np.int32))
+            out.append((int(r.request_id), int(r.status), tho, th, float(r.t_submit_us), float(r.t_done_us)))
+        return out
+
+    def pending(self):
+        q, f = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().sbt_server_pending(self.handle, ctypes.byref(q), ctypes.byref(f)), "sbt_server_pending")
+        return int(q.value), int(f.value)
+
+
+def sbt_now_us() -> float:
+    return float(lib().sbt_now_us())

@@ -35,6 +35,7 @@ event can be regenerated on its own.
 from __future__ import annotations
 
 import dataclasses
+import os
 from typing import Optional
 
 import numpy as np
@@ -218,8 +219,27 @@ def make_event(recipe: Recipe, index: int) -> dict:
                 truth=all_truth[order].astype(np.int32))
 
 
-def make_batch(config: str, n_events: Optional[int] = None, first: int = 0) -> Batch:
-    """Events ``first .. first+n_events-1`` of a named recipe, packed."""
+def _make_range(args):
+    name, lo, hi = args
+    return [make_event(CONFIGS[name], i) for i in range(lo, hi)]
+
+
+def make_batch(config: str, n_events: Optional[int] = None, first: int = 0,
+               workers: Optional[int] = None) -> Batch:
+    """Events ``first .. first+n_events-1`` of a named recipe, packed.
+
+    Large batches are drawn in ``workers`` processes (default: up to 16);
+    every event has its own random stream, so the result does not depend on
+    the number of workers."""
     recipe = CONFIGS[config]
     n = recipe.n_events if n_events is None else int(n_events)
-    return concat([make_event(recipe, first + i) for i in range(n)], PLANE_Z)
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1) if n >= 1000 else 1
+    if workers <= 1:
+        return concat([make_event(recipe, first + i) for i in range(n)], PLANE_Z)
+    import multiprocessing as mp
+    step = (n + workers * 4 - 1) // (workers * 4)
+    chunks = [(config, first + a, first + min(a + step, n)) for a in range(0, n, step)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        parts = pool.map(_make_range, chunks)
+    return concat([ev for part in parts for ev in part], PLANE_Z)

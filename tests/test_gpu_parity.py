@@ -1,0 +1,288 @@
+"""GPU parity: the HIP library against the oracle, byte for byte.
+
+Every case prints its name before touching the GPU.  Track sets are integer
+outputs, so the bar is exact equality of the three CSR arrays.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _util import event_batch, tiny_random_event
+from paper_2207_03936_amd import sbt, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    sbt.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _same(got, want, what):
+    eto, tho, th = want
+    g_eto, g_tho, g_th = got[:3]
+    assert np.array_equal(g_eto, eto), f"{what}: event track offsets differ"
+    assert np.array_equal(g_tho, tho), f"{what}: track hit offsets differ"
+    assert np.array_equal(g_th, th), f"{what}: track hits differ"
+
+
+def _first_diff(got, want):
+    eto, tho, th = want
+    for e in range(len(eto) - 1):
+        a = [tuple(th[tho[t]:tho[t + 1]]) for t in range(eto[e], eto[e + 1])]
+        b = [tuple(got[2][got[1][t]:got[1][t + 1]]) for t in range(got[0][e], got[0][e + 1])]
+        if a != b:
+            return e, a, b
+    return None
+
+
+def run_plain(batch, **kw):
+    p = sbt.make_params(batch.module_z, **kw)
+    return sbt.sbt_reconstruct(p, sbt.DeviceBatch(batch)).to_host()
+
+
+def run_batched(batch, tuning=None, **kw):
+    p = sbt.make_params(batch.module_z, **kw)
+    ctx = sbt.Context(p, max(batch.n_events, 1), max(batch.n_hits, 1), tuning)
+    out = ctx.reconstruct(sbt.DeviceBatch(batch)).to_host()
+    ctx.close()
+    return out
+
+
+# ------------------------------------------------------------------ phi sort
+
+@pytest.mark.parametrize("config,n", [("tiny", 8), ("mu7.6", 8), ("mu30", 3)])
+def test_phi_sort_matches_oracle(config, n):
+    say(f"phi sort {config} x{n}")
+    b = synth.make_batch(config, n)
+    phi, ids = sbt.sbt_debug_phi_sort(sbt.make_params(b.module_z), sbt.DeviceBatch(b))
+    M = b.n_modules
+    for e in range(b.n_events):
+        lo, hi = int(b.event_offsets[e]), int(b.event_offsets[e + 1])
+        mo = b.module_offsets[e * M:(e + 1) * M + 1] - lo
+        want_ids = oracle.sort_event(mo, b.x[lo:hi], b.y[lo:hi])
+        want_q = oracle.phi16(b.x[lo:hi], b.y[lo:hi])
+        assert np.array_equal(ids[lo:hi], want_ids)
+        assert np.array_equal(phi[lo:hi], want_q[want_ids])
+
+
+# ------------------------------------------------------------------ plain and batched vs oracle
+
+CASES = [("tiny", 20), ("mu7.6", 40), ("mu1-25", 30), ("mu30", 6)]
+
+
+@pytest.mark.parametrize("config,n", CASES)
+def test_plain_matches_oracle(config, n):
+    say(f"plain {config} x{n}")
+    b = synth.make_batch(config, n)
+    want = oracle.reconstruct(b)
+    got = run_plain(b)
+    assert not got[3].any()
+    assert _first_diff(got, want) is None, _first_diff(got, want)
+    _same(got, want, f"plain {config}")
+
+
+@pytest.mark.parametrize("config,n", CASES)
+def test_batched_matches_oracle(config, n):
+    say(f"batched {config} x{n}")
+    b = synth.make_batch(config, n)
+    want = oracle.reconstruct(b)
+    got = run_batched(b)
+    assert not got[3].any()
+    assert _first_diff(got, want) is None, _first_diff(got, want)
+    _same(got, want, f"batched {config}")
+
+
+@pytest.mark.parametrize("tpe", [64, 128, 256, 512])
+@pytest.mark.parametrize("bpc", [1, 3, 8])
+def test_batched_independent_of_launch_configuration(tpe, bpc):
+    say(f"batched tuning tpe={tpe} bpc={bpc}")
+    b = synth.make_batch("mu7.6", 24, first=100)
+    want = oracle.reconstruct(b)
+    got = run_batched(b, sbt.make_tuning(tpe, bpc))
+    _same(got, want, f"tpe={tpe} bpc={bpc}")
+
+
+def test_random_tiny_events_and_parameters():
+    """Crowded tiny events with random tolerances, traversal direction and
+    miss allowance: the same events the oracle's brute-force pins use."""
+    rng = np.random.default_rng(77)
+    for i in range(30):
+        evs = [tiny_random_event(rng, M=7, jitter_z=bool(i % 2)) for _ in range(8)]
+        b = synth.concat([dict(x=x, y=y, z=z, module_counts=np.diff(mo).astype(np.int64),
+                               truth=np.full(len(x), -1, np.int32)) for (x, y, z, mo, mz) in evs], evs[0][4])
+        kw = dict(reverse=int(rng.integers(0, 2)),
+                  max_doublet_candidates=int(rng.choice([1, 2, 4, 64])),
+                  phi_window_seeding=int(rng.choice([20, 416, 32767])),
+                  phi_window_forwarding=int(rng.choice([20, 416, 32767])),
+                  max_scatter_seeding=float(rng.choice([0.05, 1.0, 20.0])),
+                  max_scatter_forwarding=float(rng.choice([0.05, 1.0, 20.0])),
+                  max_tracklet_chi2=float(rng.choice([0.001, 0.05, 5.0])),
+                  max_consecutive_misses=int(rng.choice([0, 1, 2])))
+        say(f"random tiny batch {i} {kw}")
+        want = oracle.reconstruct(b, **kw)
+        _same(run_plain(b, **kw), want, f"plain random {i}")
+        _same(run_batched(b, **kw), want, f"batched random {i}")
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_empty_batch():
+    say("empty batch")
+    b = synth.make_batch("tiny", 0)
+    for got in (run_plain(b), run_batched(b)):
+        assert list(got[0]) == [0] and list(got[1]) == [0] and got[2].size == 0
+
+
+def test_empty_and_degenerate_events():
+    say("empty and degenerate events")
+    mz = synth.PLANE_Z.astype(np.float32)
+    empty = dict(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                 module_counts=np.zeros(26, np.int64), truth=np.zeros(0, np.int32))
+    two = dict(x=np.array([10, 10.5], np.float32), y=np.array([1, 1.05], np.float32),
+               z=np.array([mz[3], mz[4]], np.float32),
+               module_counts=np.eye(26, dtype=np.int64)[3] + np.eye(26, dtype=np.int64)[4],
+               truth=np.zeros(2, np.int32))
+    tiny = synth.make_batch("tiny", 3)
+    evs = [empty, synth._slice(tiny, 0), two, empty, synth._slice(tiny, 1), synth._slice(tiny, 2), empty]
+    b = synth.concat(evs, mz)
+    want = oracle.reconstruct(b)
+    _same(run_plain(b), want, "plain degenerate")
+    _same(run_batched(b), want, "batched degenerate")
+
+
+def test_largest_event_and_oversized_event():
+    """An event of exactly 65,535 hits is reconstructed; one of 65,536 is
+    flagged SBT_EV_TOO_LARGE with no tracks, and its neighbours are intact."""
+    say("largest and oversized events")
+    parts = []
+    k = 0
+    while sum(p["x"].size for p in parts) < 65535:
+        parts.append(synth._slice(synth.make_batch("mu30", 1, first=k), 0))
+        k += 1
+    big = synth.concat(parts, synth.PLANE_Z)
+
+    def cut(n):
+        # first n hits of the merged event (hits stay grouped by module)
+        M = big.n_modules
+        mo = np.zeros(M + 1, np.int64)
+        counts = np.zeros(M, np.int64)
+        # regroup all hits by module, then keep n of them
+        mod = np.repeat(np.tile(np.arange(M), len(parts)), np.diff(big.module_offsets))
+        order = np.argsort(mod, kind="stable")[:n]
+        order = order[np.argsort(mod[order], kind="stable")]
+        counts = np.bincount(mod[order], minlength=M)
+        return dict(x=big.x[order], y=big.y[order], z=big.z[order], module_counts=counts.astype(np.int64),
+                    truth=np.zeros(n, np.int32))
+    small = synth._slice(synth.make_batch("tiny", 1), 0)
+    b = synth.concat([small, cut(65535), small, cut(65536), small], synth.PLANE_Z)
+    ok = synth.concat([small, cut(65535), small, small], synth.PLANE_Z)
+    want_ok = oracle.reconstruct(ok)
+    for name, got in (("plain", run_plain(b)), ("batched", run_batched(b))):
+        say(f"{name}: statuses {list(got[3])}")
+        assert list(got[3]) == [0, 0, 0, sbt.SBT_EV_TOO_LARGE, 0]
+        eto, tho, th = got[:3]
+        assert eto[4] == eto[3], "oversized event produced tracks"
+        # drop the oversized event and compare the rest with the oracle
+        keep = [0, 1, 2, 4]
+        mine = [[tuple(th[tho[t]:tho[t + 1]]) for t in range(eto[e], eto[e + 1])] for e in keep]
+        ref = [[tuple(want_ok[2][want_ok[1][t]:want_ok[1][t + 1]]) for t in range(want_ok[0][e], want_ok[0][e + 1])]
+               for e in range(4)]
+        assert mine == ref, name
+
+
+def test_bad_offsets_are_reported():
+    say("bad offsets")
+    b = synth.make_batch("tiny", 3)
+    mo = b.module_offsets.copy()
+    M = b.n_modules
+    mo[M + 5] = mo[M + 7] + 3      # event 1: module offsets decrease
+    bad = synth.Batch(b.x, b.y, b.z, b.event_offsets, mo, b.module_z, b.truth)
+    want = oracle.reconstruct(synth.concat([synth._slice(b, 0), synth._slice(b, 2)], b.module_z))
+    for name, got in (("plain", run_plain(bad)), ("batched", run_batched(bad))):
+        assert list(got[3]) == [0, sbt.SBT_EV_BAD_OFFSETS, 0], name
+        assert got[0][2] == got[0][1]
+        assert list(np.delete(np.diff(got[0]), 1)) == list(np.diff(want[0]))
+
+
+# ------------------------------------------------------------------ full sizes
+
+def _sampled_equal(b, got, events):
+    sub = b.select(events)
+    want = oracle.reconstruct(sub)
+    eto, tho, th = got[:3]
+    for i, e in enumerate(events):
+        mine = [tuple(th[tho[t]:tho[t + 1]]) for t in range(eto[e], eto[e + 1])]
+        ref = [tuple(want[2][want[1][t]:want[1][t + 1]]) for t in range(want[0][i], want[0][i + 1])]
+        assert mine == ref, f"event {e}"
+
+
+def _invariants(b, got):
+    eto, tho, th = got[:3]
+    assert np.all(np.diff(eto) >= 0) and np.all(np.diff(tho) >= 3)
+    M = b.n_modules
+    for e in range(b.n_events):
+        lo, hi = int(b.event_offsets[e]), int(b.event_offsets[e + 1])
+        ids = th[tho[eto[e]]:tho[eto[e + 1]]]
+        assert ids.size == np.unique(ids).size
+        assert ids.size == 0 or (ids.min() >= 0 and ids.max() < hi - lo)
+
+
+def test_full_mu7_6_batch_all_events():
+    """The 1,000-event mu = 7.6 batch in the launch configuration the
+    benchmark times: every event against the oracle, plain and batched."""
+    say("full mu7.6 x1000")
+    b = synth.make_batch("mu7.6")
+    want = oracle.reconstruct(b)
+    p = sbt.make_params(b.module_z)
+    dev = sbt.DeviceBatch(b)
+    _same(sbt.sbt_reconstruct(p, dev).to_host(), want, "plain mu7.6 x1000")
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    for rep in range(3):       # graph capture, then replays with eager work between
+        say(f"  batched replay {rep}")
+        out.fill_(-1)
+        ctx.reconstruct(dev, out)
+        got = out.to_host()
+        _same(got, want, f"batched mu7.6 x1000 replay {rep}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("config,n,sample", [("mu1-25", 10000, 120), ("mu30", 2000, 30)])
+def test_full_size_sampled(config, n, sample):
+    say(f"full {config} x{n}, {sample} sampled events")
+    b = synth.make_batch(config, n)
+    got = run_batched(b)
+    assert not got[3].any()
+    rng = np.random.default_rng(5)
+    events = np.sort(rng.choice(b.n_events, sample, replace=False))
+    sizes = np.diff(b.event_offsets)
+    events = np.unique(np.concatenate([events, [int(np.argmax(sizes)), int(np.argmin(sizes))]]))
+    _sampled_equal(b, got, events)
+    _invariants(b, got)
+
+
+def test_repeat_runs_identical():
+    say("20 repeated batched runs")
+    b = synth.make_batch("mu30", 40)
+    p = sbt.make_params(b.module_z)
+    dev = sbt.DeviceBatch(b)
+    ctx = sbt.Context(p, b.n_events, b.n_hits, sbt.make_tuning(256, 8))
+    first = ctx.reconstruct(dev).to_host()
+    for i in range(19):
+        _same(ctx.reconstruct(dev).to_host(), first[:3], f"repeat {i}")
+    ctx.close()
