@@ -151,14 +151,18 @@ typedef struct sbt_tracks {
 /* Launch configuration of the batched path.  It never changes results.
  * threads_per_event   64, 128, 256 or 512 lanes cooperating on one event.
  * blocks_per_cu       persistent workgroups per compute unit (1..16).
- * lds_window_hits     capacity, in hits, of each LDS-staged module window;
- *                     larger modules are read from global memory (0 = the
- *                     library's default).                                  */
+ * lds_window_hits     capacity, in hits, of each of the four LDS slots that
+ *                     hold the phi-sorted hits of consecutive modules
+ *                     (0..2048); a larger module is read from memory.
+ * lds_owner_hits      events with at most this many hits keep their hit
+ *                     flags (one bit per hit) in LDS, larger ones in
+ *                     memory (0..65536).
+ * The two LDS capacities together take at most 159 KiB per workgroup.    */
 typedef struct sbt_tuning {
     int32_t threads_per_event;
     int32_t blocks_per_cu;
     int32_t lds_window_hits;
-    int32_t reserved;
+    int32_t lds_owner_hits;
 } sbt_tuning;
 
 /* Message for a return code (static storage). */

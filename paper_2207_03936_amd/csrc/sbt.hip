@@ -26,26 +26,30 @@ using namespace sbt;
 // plain form ----------------------------------------------------------------
 
 template <int B>
-__global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W)
+__global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
 {
     __shared__ Shared<B> S;
+    extern __shared__ char dyn[];
+    const Lds L = carve_lds(dyn, cap, own_cap);
     const int e = blockIdx.x;
     int hb, N;
     const int st = load_event<B>(P, H, e, S, &hb, &N);
     if (threadIdx.x == 0) W.ev_st[e] = st;
     if (st != 0) return;
-    stage_sort<B>(P, H, W, hb, N, S);
+    stage_sort<B>(P, H, W, hb, N, S, L);
 }
 
 template <int B>
-__global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W)
+__global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
 {
     __shared__ Shared<B> S;
+    extern __shared__ char dyn[];
+    const Lds L = carve_lds(dyn, cap, own_cap);
     const int e = blockIdx.x;
     if (W.ev_st[e] != 0) return;
     int hb, N;
     load_event<B>(P, H, e, S, &hb, &N);
-    stage_track<B>(P, H, W, hb, N, S);
+    stage_track<B>(P, W, e, hb, N, S, L, true);
     if (threadIdx.x == 0) W.ev_nfin[e] = S.cnt[3];
 }
 
@@ -55,7 +59,7 @@ __global__ __launch_bounds__(B) void k_weak_filter(sbt_params P, HitsArgs H, Wor
     const int e = blockIdx.x;
     if (W.ev_st[e] != 0) return;
     const int hb = H.eo[e];
-    stage_filter<B>(P, W, hb, W.ev_nfin[e]);
+    stage_filter<B>(P, W, hb, W.ev_nfin[e], owner_words(W, e, hb));
 }
 
 template <int B>
@@ -73,27 +77,60 @@ __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
 
 // batched form ----------------------------------------------------------------
 
-__global__ void k_reset_counter(unsigned int *counter)
+// Resets the work counter and orders the events by size, largest first, so
+// the persistent workgroups start the longest events early (the order of
+// processing never changes an event's result).  Counting sort on N / 64.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderClasses = 1024;
+__global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0u;
+    __shared__ int hist[kOrderClasses + 1];
+    __shared__ int fill[kOrderClasses];
+    __shared__ int sw[kOrderThreads / 64 + 1];
+    if (threadIdx.x == 0) *W.counter = 0u;
+    for (int i = threadIdx.x; i <= kOrderClasses; i += kOrderThreads) hist[i] = 0;
+    for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) fill[i] = 0;
+    __syncthreads();
+    const int E = H.n_events;
+    for (int e = threadIdx.x; e < E; e += kOrderThreads) {
+        int n = H.eo[e + 1] - H.eo[e];
+        int cls = n < 0 ? 0 : (n >> 6);
+        cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
+        atomicAdd(&hist[kOrderClasses - 1 - cls], 1);
+    }
+    __syncthreads();
+    block_scan_inplace<kOrderThreads>(hist, kOrderClasses + 1, sw);
+    __syncthreads();
+    for (int e = threadIdx.x; e < E; e += kOrderThreads) {
+        int n = H.eo[e + 1] - H.eo[e];
+        int cls = n < 0 ? 0 : (n >> 6);
+        cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
+        const int k = kOrderClasses - 1 - cls;
+        W.order[hist[k] + atomicAdd(&fill[k], 1)] = e;
+    }
 }
 
 template <int B>
-__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W)
+__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
 {
     __shared__ Shared<B> S;
+    extern __shared__ char dyn[];
+    const Lds L = carve_lds(dyn, cap, own_cap);
     for (;;) {
-        if (threadIdx.x == 0) S.e = (int)atomicAdd(W.counter, 1u);
+        if (threadIdx.x == 0) {
+            const int idx = (int)atomicAdd(W.counter, 1u);
+            S.e = idx < H.n_events ? W.order[idx] : -1;
+        }
         __syncthreads();
-        const int e = S.e;
-        if (e >= H.n_events) break;
+        const int e = uni(S.e);
+        if (e < 0) break;
         int hb, N;
         const int st = load_event<B>(P, H, e, S, &hb, &N);
         if (threadIdx.x == 0) W.ev_st[e] = st;
         if (st == 0) {
-            stage_sort<B>(P, H, W, hb, N, S);
-            stage_track<B>(P, H, W, hb, N, S);
-            stage_filter<B>(P, W, hb, S.cnt[3]);
+            stage_sort<B>(P, H, W, hb, N, S, L);
+            stage_track<B>(P, W, e, hb, N, S, L, false);
+            stage_filter<B>(P, W, hb, uni(S.cnt[3]), owner_ptr(L, W, e, hb, N));
             stage_compact<B>(W, e, hb, N, S.scan);
         } else if (threadIdx.x == 0) {
             W.ev_nt[e] = 0;
@@ -175,24 +212,26 @@ size_t carve(int32_t E, int32_t H, char *base, Work *W)
     const size_t h = (size_t)(H > 0 ? H : 1);
     const size_t e = (size_t)(E > 0 ? E : 1);
     Work w;
-    w.q = (uint16_t *)take(2 * h);
-    w.bucket = (uint16_t *)take(2 * h);
+    w.keys = (uint32_t *)take(4 * h);
     w.sx = (float *)take(4 * h);
     w.sy = (float *)take(4 * h);
     w.sz = (float *)take(4 * h);
     w.sq = (uint16_t *)take(2 * h);
     w.sid = (uint16_t *)take(2 * h);
-    w.owner = (uint16_t *)take(2 * h);
+    w.owner = (uint32_t *)take(4 * (h / 32 + e + 2));
     w.claim = (unsigned long long *)take(8 * h);
     w.prev = (uint16_t *)take(2 * h);
     w.rec = (Rec *)take(sizeof(Rec) * h);
-    w.rbest = (uint16_t *)take(2 * h);
+    w.rbest = (uint32_t *)take(4 * h);
     w.rbsc = (float *)take(4 * h);
     w.rchi2 = (float *)take(4 * h);
     w.rflag = (uint8_t *)take(h);
     w.act0 = (uint16_t *)take(2 * h);
     w.act1 = (uint16_t *)take(2 * h);
     w.fin = (uint16_t *)take(2 * h);
+    w.freel = (uint16_t *)take(2 * h);
+    w.freem = (uint16_t *)take(2 * h);
+    w.frank = (uint16_t *)take(2 * h);
     w.key2rec = (uint16_t *)take(2 * h);
     w.st_hits = (uint16_t *)take(2 * h);
     w.st_toff = (int32_t *)take(4 * h);
@@ -201,12 +240,16 @@ size_t carve(int32_t E, int32_t H, char *base, Work *W)
     w.ev_hb = (int32_t *)take(4 * e);
     w.ev_st = (int32_t *)take(4 * e);
     w.ev_nfin = (int32_t *)take(4 * e);
+    w.order = (int32_t *)take(4 * e);
     w.counter = (unsigned int *)take(256);
     if (W) *W = w;
     return off;
 }
 
 bool is_pow_tpe(int v) { return v == 64 || v == 128 || v == 256 || v == 512; }
+
+// dynamic LDS a workgroup may ask for (gfx950: 160 KiB per compute unit)
+constexpr size_t kMaxDynLds = 160 * 1024 - 1024;
 
 int check_hits(const sbt_hits *h)
 {
@@ -253,11 +296,16 @@ OutArgs out_args(const sbt_tracks *t)
 
 constexpr int kPlainThreads = 256;
 
+constexpr int kPlainCap = 672;
+constexpr int kPlainOwnCap = 16384;
+
 int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hipStream_t s)
 {
     const dim3 g(H.n_events), b(kPlainThreads);
-    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, 0, s, P, H, W);
-    hipLaunchKernelGGL(k_seed_follow<kPlainThreads>, g, b, 0, s, P, H, W);
+    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, lds_bytes(kPlainCap, kPlainOwnCap), s, P, H, W, kPlainCap,
+                       kPlainOwnCap);
+    hipLaunchKernelGGL(k_seed_follow<kPlainThreads>, g, b, lds_bytes(kPlainCap, kPlainOwnCap), s, P, H, W,
+                       kPlainCap, kPlainOwnCap);
     hipLaunchKernelGGL(k_weak_filter<kPlainThreads>, g, b, 0, s, P, H, W);
     hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, 0, s, H, W);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
@@ -271,7 +319,7 @@ int launch_tail(const HitsArgs &H, const Work &W, const OutArgs &O, hipStream_t 
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
 }
 
-typedef void (*persistent_fn)(sbt_params, HitsArgs, Work);
+typedef void (*persistent_fn)(sbt_params, HitsArgs, Work, int, int);
 
 persistent_fn persistent_kernel(int tpe)
 {
@@ -292,14 +340,26 @@ int device_cus(int *cus)
     return SBT_OK;
 }
 
+// Allows dynamic LDS above 64 KiB for the persistent kernel of this width.
+int allow_lds(int tpe, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return SBT_OK;
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(persistent_kernel(tpe)),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return SBT_OK;
+}
+
 int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
 {
+    const size_t lds = lds_bytes(T.lds_window_hits, T.lds_owner_hits);
+    if (int rc = allow_lds(T.threads_per_event, lds)) return rc;
     int cus = 0;
     int rc = device_cus(&cus);
     if (rc) return rc;
     int occ = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void *>(persistent_kernel(T.threads_per_event)), T.threads_per_event, 0));
+        &occ, reinterpret_cast<const void *>(persistent_kernel(T.threads_per_event)), T.threads_per_event,
+        lds_bytes(T.lds_window_hits, T.lds_owner_hits)));
     int bpc = std::max(1, std::min(T.blocks_per_cu, std::max(occ, 1)));
     *grid = std::max(1, std::min(cus * bpc, std::max(n_events, 1)));
     return SBT_OK;
@@ -312,9 +372,10 @@ int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, 
     int rc = persistent_grid(T, H.n_events, &grid);
     if (rc) return rc;
     if (marks) HIP_TRY(hipEventRecord(marks[0], s));
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, W.counter);
-    hipLaunchKernelGGL(persistent_kernel(T.threads_per_event), dim3(grid), dim3(T.threads_per_event), 0, s,
-                       P, H, W);
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
+    hipLaunchKernelGGL(persistent_kernel(T.threads_per_event), dim3(grid), dim3(T.threads_per_event),
+                       lds_bytes(T.lds_window_hits, T.lds_owner_hits), s, P, H, W, T.lds_window_hits,
+                       T.lds_owner_hits);
     if (marks) HIP_TRY(hipEventRecord(marks[1], s));
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, H, W, O);
     if (marks) HIP_TRY(hipEventRecord(marks[2], s));
@@ -432,7 +493,8 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
     Work W;
     carve(hits->n_events, hits->n_hits, (char *)workspace, &W);
     const HitsArgs H = hits_args(hits);
-    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, dim3(H.n_events), dim3(kPlainThreads), 0, s, *params, H, W);
+    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, dim3(H.n_events), dim3(kPlainThreads),
+                       lds_bytes(kPlainCap, kPlainOwnCap), s, *params, H, W, kPlainCap, kPlainOwnCap);
     hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
                        phi_sorted, ids_sorted);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
@@ -477,7 +539,9 @@ int valid_tuning(const sbt_tuning &t)
 {
     if (!is_pow_tpe(t.threads_per_event)) return SBT_ERR_INVALID_ARG;
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return SBT_ERR_INVALID_ARG;
-    if (t.lds_window_hits < 0) return SBT_ERR_INVALID_ARG;
+    if (t.lds_window_hits < 0 || t.lds_window_hits > 2048) return SBT_ERR_INVALID_ARG;
+    if (t.lds_owner_hits < 0 || t.lds_owner_hits > 65536) return SBT_ERR_INVALID_ARG;
+    if (lds_bytes(t.lds_window_hits, t.lds_owner_hits) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
     return SBT_OK;
 }
 
@@ -485,9 +549,9 @@ sbt_tuning default_tuning()
 {
     sbt_tuning t;
     t.threads_per_event = 256;
-    t.blocks_per_cu = 4;
-    t.lds_window_hits = 0;
-    t.reserved = 0;
+    t.blocks_per_cu = 3;
+    t.lds_window_hits = 672;
+    t.lds_owner_hits = 16384;
     return t;
 }
 
@@ -644,38 +708,48 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
         (void)hipEventDestroy(t0);
         return SBT_ERR_HIP;
     }
-    const int tpes[] = {64, 128, 256, 512};
-    const int bpcs[] = {1, 2, 4, 8, 16};
+    // candidates: lanes per event x LDS slot capacity, each at the largest
+    // number of resident workgroups per CU and one less
+    const int tpes[] = {128, 256, 512};
+    const int caps[] = {448, 672, 1024, 1536};
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;
     rc = SBT_OK;
     for (int tpe : tpes) {
-        int occ = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(persistent_kernel(tpe)),
-                                                          tpe, 0) != hipSuccess) {
-            rc = SBT_ERR_HIP;
-            break;
-        }
-        for (int bpc : bpcs) {
-            if (bpc > std::max(occ, 1)) continue;
+        for (int cap : caps) {
             sbt_tuning t = c->tuning;
             t.threads_per_event = tpe;
-            t.blocks_per_cu = bpc;
-            if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
-            if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
-            for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);
-            if (rc) break;
-            float ms = 0.0f;
-            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
-                hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+            t.lds_window_hits = cap;
+            t.lds_owner_hits = 16384;
+            if (valid_tuning(t) != SBT_OK) continue;
+            const size_t lds = lds_bytes(cap, t.lds_owner_hits);
+            if ((rc = allow_lds(tpe, lds))) break;
+            int occ = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &occ, reinterpret_cast<const void *>(persistent_kernel(tpe)), tpe, lds) != hipSuccess) {
                 rc = SBT_ERR_HIP;
                 break;
             }
-            ms /= (float)reps;
-            if (win_ms < 0.0f || ms < win_ms) {
-                win_ms = ms;
-                win = t;
+            if (occ < 1) continue;
+            for (int bpc = occ; bpc >= 1 && bpc >= occ - 1; --bpc) {
+                t.blocks_per_cu = bpc;
+                if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
+                if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
+                for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);
+                if (rc) break;
+                float ms = 0.0f;
+                if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+                    rc = SBT_ERR_HIP;
+                    break;
+                }
+                ms /= (float)reps;
+                if (win_ms < 0.0f || ms < win_ms) {
+                    win_ms = ms;
+                    win = t;
+                }
             }
+            if (rc) break;
         }
         if (rc) break;
     }

@@ -8,7 +8,9 @@
 // Per-event state lives in the workspace, in regions indexed by the event's
 // absolute hit offset hb (capacity N = hits of the event):
 //   sorted hits   sx, sy, sz, sq (phi16), sid (event-local id)   by sorted position
-//   owner         u16 per hit id: 0xFFFF (free) or the key of the track owning it
+//   owner         one bit per hit id: set once a track has taken the hit (the
+//                 method only ever asks whether a hit is flagged; which track
+//                 holds it is settled by the claim keys)
 //   claim         u64 per hit id: minimum claim key of the current stage
 //   prev          u16 per hit id: previous hit of the owning track
 //   rec           32-byte forming-track records (one per seed; <= N)
@@ -38,28 +40,30 @@ struct Rec {
 static_assert(sizeof(Rec) == 32, "record layout");
 
 // record flags
-constexpr uint8_t kFlagSeedClaim = 1;  // claimed its three seed hits this stage
 constexpr uint8_t kFlagCandidate = 2;  // tracklet candidate
 constexpr uint8_t kFlagAccepted = 4;
 
 struct Work {
-    uint16_t *q;        // phi16 by id (sort scratch)
-    uint16_t *bucket;   // sort bucket scratch
+    uint32_t *keys;     // sort keys (phi16 << 16 | id) of events too large for LDS
     float *sx, *sy, *sz;
     uint16_t *sq, *sid;
-    uint16_t *owner;
+    uint32_t *owner;    // flag bitmaps; event e's starts at word (hb >> 5) + e
     unsigned long long *claim;
     uint16_t *prev;
     Rec *rec;
-    uint16_t *rbest;
+    uint32_t *rbest;    // best hit id | window position << 16, or ~0
     float *rbsc;
     float *rchi2;
     uint8_t *rflag;
     uint16_t *act0, *act1, *fin;
+    uint16_t *freel;    // unflagged-position lists of modules too large for LDS
+    uint16_t *freem;
+    uint16_t *frank;
     uint16_t *key2rec;
     uint16_t *st_hits;  // per-event compacted hit ids
     int32_t *st_toff;   // per-event track hit offsets
     int32_t *ev_nt, *ev_nh, *ev_hb, *ev_st, *ev_nfin;
+    int32_t *order;     // events, largest first (batched form)
     unsigned int *counter;
 };
 
@@ -114,6 +118,10 @@ __device__ __forceinline__ uint16_t phi16(float x, float y)
 }
 
 // ---------------------------------------------------------------- small helpers
+// A value every lane of the wave holds alike (read from LDS, for instance),
+// moved to a scalar register.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ int kmod(const sbt_params &P, int t)
 {
     return P.reverse ? P.n_modules - 1 - t : t;
@@ -130,6 +138,17 @@ __device__ __forceinline__ int module_of(const int *mo, int M, int i)
     return lo;
 }
 
+// hit flags: one bit per event-local hit id
+__device__ __forceinline__ bool is_free(const uint32_t *own, unsigned id)
+{
+    return ((own[id >> 5] >> (id & 31u)) & 1u) == 0u;
+}
+
+__device__ __forceinline__ void set_flag(uint32_t *own, unsigned id)
+{
+    atomicOr(&own[id >> 5], 1u << (id & 31u));
+}
+
 __device__ __forceinline__ int lower_bound16(const uint16_t *a, int n, uint16_t v)
 {
     int lo = 0, hi = n;
@@ -140,11 +159,16 @@ __device__ __forceinline__ int lower_bound16(const uint16_t *a, int n, uint16_t 
     return lo;
 }
 
-__device__ __forceinline__ unsigned long long claim_key(float score, uint16_t key)
+// Claim key of a stage: (255 - stage) in bits 48..55, the score's binary32
+// bits in 16..47 (scores are >= +0, so the bits order like the values) and
+// the track key in 0..15.  Within a stage the order is (score, key); a claim
+// left from an earlier stage is larger than any claim of a later one, so the
+// claim words never need clearing between stages.
+__device__ __forceinline__ unsigned long long claim_key(float score, uint16_t key, int stage)
 {
-    // scores are >= +0, so their binary32 bits order like their values
-    return ((unsigned long long)__float_as_uint(score) << 32) | key;
+    return ((unsigned long long)(255 - stage) << 48) | ((unsigned long long)__float_as_uint(score) << 16) | key;
 }
+constexpr int kFilterStage = 64;
 
 // Append under a predicate with one LDS atomic per wave; every lane of the
 // wave must call it.  Returns the slot, or -1 where pred is false.
@@ -214,16 +238,73 @@ __device__ void block_scan_inplace(int *a, int n, int *s_w)
     }
 }
 
-// sort bins: 4096 in total, a power of two per module
+// sort bins: 1024 in total, a power of two per module
+constexpr int kSortBins = 1024;
 __host__ __device__ __forceinline__ int sort_shift(int M)
 {
-    int bits = 6;                       // M <= 64 -> at least 64 bins per module
-    while (bits < 12 && (M << (bits + 1)) <= 4096) ++bits;
+    int bits = 4;                       // M <= 64 -> at least 16 bins per module
+    while (bits < 12 && (M << (bits + 1)) <= kSortBins) ++bits;
     return 16 - bits;
 }
-constexpr int kSortBins = 4096;
 
-// LDS shared by the stages of one event
+// Dynamic LDS of one event workgroup.  The sort scratch (histogram, fill
+// counters and the 32-bit sort keys of events with at most sortcap hits)
+// aliases the module ring, which is filled only after the sort.
+//   ring  4 slots x cap hits: phi16, id, x, y, z (16 B per hit)
+//   freel unflagged positions of the seeding stage's doublet module
+//   frank rank of each doublet-module position among its unflagged positions
+//   own   hit-flag bitmap of the event when N <= own_cap
+struct Lds {
+    int cap, own_cap, sortcap;
+    uint32_t *keys;
+    uint16_t *rq, *rid;
+    float *rx, *ry, *rz;
+    uint16_t *freel;     // unflagged positions of the doublet module (cap entries)
+    uint16_t *freem;     // unflagged positions of the middle module (cap entries)
+    uint16_t *frank;     // unflagged positions before each doublet-module position
+    uint32_t *own;
+    int *hist, *fill;
+};
+
+__host__ __device__ __forceinline__ size_t lds_align(size_t v) { return (v + 15) & ~size_t(15); }
+
+__host__ __device__ __forceinline__ size_t lds_ring_bytes(int cap)
+{
+    return lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2);
+}
+
+__host__ __device__ __forceinline__ size_t lds_sort_head() { return lds_align((size_t)(2 * kSortBins + 1) * 4); }
+
+__host__ __device__ __forceinline__ size_t lds_bytes(int cap, int own_cap)
+{
+    const size_t sort = lds_sort_head() + 4 * 1024;   // room for the keys of 1,024 hits at least
+    const size_t track = lds_ring_bytes(cap) + lds_align((size_t)((own_cap + 31) / 32) * 4);
+    return sort > track ? sort : track;
+}
+
+__device__ __forceinline__ Lds carve_lds(char *base, int cap, int own_cap)
+{
+    Lds L;
+    L.cap = cap;
+    L.own_cap = own_cap;
+    L.sortcap = (int)((lds_bytes(cap, own_cap) - lds_sort_head()) / 4);
+    L.keys = (uint32_t *)(base + lds_sort_head());
+    const int c4 = 4 * cap;
+    L.rx = (float *)base;
+    L.ry = L.rx + c4;
+    L.rz = L.ry + c4;
+    L.rq = (uint16_t *)(L.rz + c4);
+    L.rid = L.rq + c4;
+    L.freel = (uint16_t *)(base + lds_align((size_t)4 * cap * 16));
+    L.freem = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + lds_align((size_t)cap * 2));
+    L.frank = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 2 * lds_align((size_t)cap * 2));
+    L.own = (uint32_t *)(base + lds_ring_bytes(cap));
+    L.hist = (int *)base;
+    L.fill = L.hist + kSortBins + 1;
+    return L;
+}
+
+// static LDS shared by the stages of one event
 template <int B>
 struct Shared {
     int mo[SBT_MAX_MODULES + 1];
@@ -231,8 +312,9 @@ struct Shared {
     int status;
     int e;
     int scan[B / 64 + 1];
-    int hist[kSortBins + 1];
-    int fill[kSortBins];
+    int slot_n[4];       // hits of the module held by each ring slot
+    int slot_g[4];       // its event-local offset
+    int slot_lds[4];     // 1: staged in LDS, 0: read from the sorted arrays in memory
 };
 
 // ---------------------------------------------------------------- validation
@@ -261,57 +343,53 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
         S.status = (int)st;
     }
     __syncthreads();
-    *hb_out = lo;
-    *n_out = hi - lo;
-    return S.status;
+    *hb_out = uni(lo);
+    *n_out = uni(hi - lo);
+    return uni(S.status);
 }
 
 // ---------------------------------------------------------------- sort by phi
-// Counting sort on (module, top bits of phi16), then each hit's rank inside
-// its bin by counting the bin members with a smaller (phi16, id) key.
+// Counting sort on (module, top bits of phi16) into buckets of 32-bit keys
+// phi16 << 16 | id, then each key's rank inside its bucket by counting the
+// smaller keys of the bucket; ties in phi16 fall to the lower id because the
+// id is the key's low half.
 template <int B>
 __device__ void stage_sort(const sbt_params &P, const HitsArgs &H, const Work &W, int hb, int N,
-                           Shared<B> &S)
+                           Shared<B> &S, const Lds &L)
 {
     const int M = P.n_modules;
     const int shift = sort_shift(M);
     const int bpm = 1 << (16 - shift);
     const int nb = M * bpm;
-    for (int i = threadIdx.x; i <= nb; i += B) S.hist[i] = 0;
-    for (int i = threadIdx.x; i < nb; i += B) S.fill[i] = 0;
+    int *hist = L.hist, *fill = L.fill;
+    uint32_t *keys = N <= L.sortcap ? L.keys : W.keys + hb;
+    for (int i = threadIdx.x; i <= nb; i += B) hist[i] = 0;
+    for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
     __syncthreads();
     const float *__restrict__ X = H.x + hb;
     const float *__restrict__ Y = H.y + hb;
     const float *__restrict__ Z = H.z + hb;
-    uint16_t *__restrict__ q = W.q + hb;
-    uint16_t *__restrict__ bucket = W.bucket + hb;
     for (int i = threadIdx.x; i < N; i += B) {
-        uint16_t qi = phi16(X[i], Y[i]);
-        q[i] = qi;
-        int k = module_of(S.mo, M, i);
-        atomicAdd(&S.hist[k * bpm + (qi >> shift)], 1);
+        const uint16_t qi = phi16(X[i], Y[i]);
+        atomicAdd(&hist[module_of(S.mo, M, i) * bpm + (qi >> shift)], 1);
     }
     __syncthreads();
-    block_scan_inplace<B>(S.hist, nb + 1, S.scan);
+    block_scan_inplace<B>(hist, nb + 1, S.scan);
     __syncthreads();
     for (int i = threadIdx.x; i < N; i += B) {
-        uint16_t qi = q[i];
-        int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
-        int slot = S.hist[bin] + atomicAdd(&S.fill[bin], 1);
-        bucket[slot] = (uint16_t)i;
+        const uint16_t qi = phi16(X[i], Y[i]);
+        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
+        keys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < N; i += B) {
-        uint16_t qi = q[i];
-        int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
-        int lo = S.hist[bin], hi = S.hist[bin + 1];
-        uint32_t key = ((uint32_t)qi << 16) | (uint32_t)i;
+    for (int s = threadIdx.x; s < N; s += B) {
+        const uint32_t key = keys[s];
+        const int i = (int)(key & 0xFFFFu);
+        const uint16_t qi = (uint16_t)(key >> 16);
+        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
+        const int lo = hist[bin], hi = hist[bin + 1];
         int rank = lo;
-        for (int s = lo; s < hi; ++s) {
-            uint32_t j = bucket[s];
-            uint32_t kj = ((uint32_t)q[j] << 16) | j;
-            rank += kj < key;
-        }
+        for (int m = lo; m < hi; ++m) rank += keys[m] < key;
         W.sx[hb + rank] = X[i];
         W.sy[hb + rank] = Y[i];
         W.sz[hb + rank] = Z[i];
@@ -321,91 +399,280 @@ __device__ void stage_sort(const sbt_params &P, const HitsArgs &H, const Work &W
     __syncthreads();
 }
 
+// ---------------------------------------------------------------- module ring
+// Traversal index u lives in ring slot u & 3.  A module with more hits than a
+// slot holds is read from the sorted arrays in memory instead.
+struct Win {
+    const uint16_t *q, *id;
+    const float *x, *y, *z;
+    int n;
+};
+
+template <int B>
+__device__ __forceinline__ Win window(const Lds &L, const Shared<B> &S, const Work &W, int hb, int u)
+{
+    const int s = u & 3;
+    Win w;
+    w.n = uni(S.slot_n[s]);
+    if (uni(S.slot_lds[s])) {
+        const int o = s * L.cap;
+        w.q = L.rq + o; w.id = L.rid + o; w.x = L.rx + o; w.y = L.ry + o; w.z = L.rz + o;
+    } else {
+        const int g = hb + uni(S.slot_g[s]);
+        w.q = W.sq + g; w.id = W.sid + g; w.x = W.sx + g; w.y = W.sy + g; w.z = W.sz + g;
+    }
+    return w;
+}
+
+// registers holding one module on its way into the ring
+template <int B>
+struct RingStage {
+    static constexpr int PF = (512 + B - 1) / B;
+    uint16_t q[PF], id[PF];
+    float x[PF], y[PF], z[PF];
+};
+
+template <int B>
+__device__ __forceinline__ void ring_load(const sbt_params &P, const Work &W, int hb, int u, const Shared<B> &S,
+                                          const Lds &L, RingStage<B> &R)
+{
+    const int k = kmod(P, u);
+    const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
+    if (n > L.cap) return;
+#pragma unroll
+    for (int j = 0; j < RingStage<B>::PF; ++j) {
+        const int i = (int)threadIdx.x + j * B;
+        if (i < n) {
+            R.q[j] = W.sq[hb + g + i];
+            R.id[j] = W.sid[hb + g + i];
+            R.x[j] = W.sx[hb + g + i];
+            R.y[j] = W.sy[hb + g + i];
+            R.z[j] = W.sz[hb + g + i];
+        }
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void ring_store(const sbt_params &P, const Work &W, int hb, int u, Shared<B> &S,
+                                           const Lds &L, const RingStage<B> &R)
+{
+    const int k = kmod(P, u);
+    const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
+    const int s = u & 3;
+    const bool lds = n <= L.cap;
+    if (threadIdx.x == 0) {
+        S.slot_n[s] = n;
+        S.slot_g[s] = g;
+        S.slot_lds[s] = lds ? 1 : 0;
+    }
+    if (!lds) return;
+    const int o = s * L.cap;
+#pragma unroll
+    for (int j = 0; j < RingStage<B>::PF; ++j) {
+        const int i = (int)threadIdx.x + j * B;
+        if (i < n) {
+            L.rq[o + i] = R.q[j];
+            L.rid[o + i] = R.id[j];
+            L.rx[o + i] = R.x[j];
+            L.ry[o + i] = R.y[j];
+            L.rz[o + i] = R.z[j];
+        }
+    }
+    for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {
+        L.rq[o + i] = W.sq[hb + g + i];
+        L.rid[o + i] = W.sid[hb + g + i];
+        L.rx[o + i] = W.sx[hb + g + i];
+        L.ry[o + i] = W.sy[hb + g + i];
+        L.rz[o + i] = W.sz[hb + g + i];
+    }
+}
+
 // ---------------------------------------------------------------- seeding
 // Seeding(t), t >= 2 (Section 3): modules A = kmod(t-2), Bm = kmod(t-1),
 // C = kmod(t).  One lane per middle hit of Bm.
-template <int B>
-__device__ void stage_seeding(const sbt_params &P, const HitsArgs &H, const Work &W, int hb, int t,
-                              Shared<B> &S, uint16_t *nxt, int *n_nxt)
+// The pendulum search visits the doublet module's phi-sorted positions in
+// the order s0, s0-1, s0+1, s0-2, s0+2, ... (wrapping, at most n visits) and
+// keeps the first K unflagged ones.  Here the unflagged positions are first
+// compacted in order; the K kept ones are then the K of smallest visit rank
+// (offset o >= 0 -> 2o, o < 0 -> -2o-1), found by merging the walks up and
+// down from s0 through the compacted list.  Returns the position of the
+// c-th kept partner, or -1.
+__device__ __forceinline__ int pendulum_pick(const uint16_t *F, int nf, int j, int s0, int na, int hu, int hd, int c)
 {
-    const int A = kmod(P, t - 2), Bm = kmod(P, t - 1), C = kmod(P, t);
-    const int a0 = S.mo[A], na = S.mo[A + 1] - a0;
-    const int b0 = S.mo[Bm], nbm = S.mo[Bm + 1] - b0;
-    const int c0 = S.mo[C], nc = S.mo[C + 1] - c0;
-    const float Zc = P.module_z[C];
+    int su = 0, sd = 0, pos = -1;
+    for (int step = 0; step <= c; ++step) {
+        int vu = 0x7fffffff, vd = 0x7fffffff, pu = 0, pd = 0;
+        if (su < nf) {
+            int ix = j + su;
+            if (ix >= nf) ix -= nf;
+            pu = F[ix];
+            int o = pu - s0;
+            if (o < 0) o += na;
+            if (o <= hu) vu = 2 * o;
+        }
+        if (sd < nf) {
+            int ix = j - 1 - sd;
+            if (ix < 0) ix += nf;
+            pd = F[ix];
+            int o = s0 - pd;
+            if (o < 0) o += na;
+            if (o >= 1 && o <= hd) vd = 2 * o - 1;
+        }
+        if (vu == 0x7fffffff && vd == 0x7fffffff) return -1;
+        if (vd == 0x7fffffff || vu < vd) { pos = pu; ++su; }
+        else { pos = pd; ++sd; }
+    }
+    return pos;
+}
+
+// best third hit for one doublet (h0 at wa position pos, h1 = middle hit)
+struct SeedBest {
+    float sc;
+    uint16_t id0, id2;
+    int pos0, pos2;
+    bool found;
+};
+
+__device__ __forceinline__ bool seed_better(const SeedBest &a, const SeedBest &b)
+{
+    if (a.found != b.found) return a.found;
+    if (!a.found) return false;
+    if (a.sc != b.sc) return a.sc < b.sc;
+    if (a.id0 != b.id0) return a.id0 < b.id0;
+    return a.id2 < b.id2;
+}
+
+__device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const uint32_t *own, int pos0, float x1,
+                                             float y1, float z1, float Zc, float Ss, uint16_t Ws, uint16_t span,
+                                             SeedBest &b)
+{
+    const uint16_t id0 = wa.id[pos0];
+    const float x0 = wa.x[pos0], y0 = wa.y[pos0], z0 = wa.z[pos0];
+    const float d01 = z1 - z0;
+    const float tx = (x1 - x0) / d01;
+    const float ty = (y1 - y0) / d01;
+    const float dzc = Zc - z1;
+    const uint16_t qe = phi16(x1 + tx * dzc, y1 + ty * dzc);
+    const int nc = wc.n;
+    if (nc == 0) return;
+    const uint16_t lo = (uint16_t)(qe - Ws);
+    int st = lower_bound16(wc.q, nc, lo);
+    if (st == nc) st = 0;
+    for (int jj = 0; jj < nc; ++jj) {
+        int pc = st + jj;
+        if (pc >= nc) pc -= nc;
+        const uint16_t qc = wc.q[pc];
+        if ((uint16_t)(qc - lo) > span) break;
+        const uint16_t id2 = wc.id[pc];
+        if (!is_free(own, id2)) continue;
+        const float dz = wc.z[pc] - z1;
+        const float dx = (x1 + tx * dz) - wc.x[pc];
+        const float dy = (y1 + ty * dz) - wc.y[pc];
+        const float sc = (dx * dx) + (dy * dy);
+        if (!(sc < Ss)) continue;
+        if (!b.found || sc < b.sc || (sc == b.sc && (id0 < b.id0 || (id0 == b.id0 && id2 < b.id2)))) {
+            b.found = true;
+            b.sc = sc;
+            b.id0 = id0;
+            b.id2 = id2;
+            b.pos0 = pos0;
+            b.pos2 = pc;
+        }
+    }
+}
+
+// Seeding(t), t >= 2 (Section 3): modules A = kmod(t-2), Bm = kmod(t-1),
+// C = kmod(t).  Work items are (unflagged middle hit, partner rank c): with
+// K a power of two up to 16, the K doublets of a middle hit run on K adjacent
+// lanes and their best triplets are reduced with lane shuffles; otherwise
+// one lane handles all K doublets of its middle hit.
+template <int B>
+__device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
+                              const uint32_t *own, uint16_t *nxt, int *n_nxt)
+{
+    const Win wa = window<B>(L, S, W, hb, t - 2);
+    const Win wb = window<B>(L, S, W, hb, t - 1);
+    const Win wc = window<B>(L, S, W, hb, t);
+    const int na = wa.n, nbm = wb.n;
+    const float Zc = P.module_z[kmod(P, t)];
     const float Ss = P.max_scatter_seeding;
     const int K = P.max_doublet_candidates;
     const uint16_t Ws = (uint16_t)P.phi_window_seeding;
     const uint16_t span = (uint16_t)(2 * P.phi_window_seeding);
-    const uint16_t *__restrict__ owner = W.owner + hb;
-    const float *sx = W.sx + hb, *sy = W.sy + hb, *sz = W.sz + hb;
-    const uint16_t *sq = W.sq + hb, *sid = W.sid + hb;
 
-    for (int base = 0; base < nbm; base += B) {
-        const int p1 = base + (int)threadIdx.x;
-        bool found = false;
-        float bsc = 0.0f;
-        uint16_t b0id = kNone, b2id = kNone, id1 = kNone;
-        float x0b = 0, y0b = 0, z0b = 0, x2b = 0, y2b = 0, z2b = 0, x1 = 0, y1 = 0, z1 = 0;
-        if (p1 < nbm && na > 0) {
-            id1 = sid[b0 + p1];
-            if (owner[id1] == kNone) {
-                x1 = sx[b0 + p1]; y1 = sy[b0 + p1]; z1 = sz[b0 + p1];
-                const uint16_t q1 = sq[b0 + p1];
-                int s0 = lower_bound16(sq + a0, na, q1);
-                if (s0 == na) s0 = 0;
-                int got = 0;
-                for (int v = 0; v < na && got < K; ++v) {
-                    int off = (v & 1) ? -((v + 1) >> 1) : (v >> 1);
-                    int pos = s0 + off;
-                    if (pos < 0) pos += na;
-                    else if (pos >= na) pos -= na;
-                    const uint16_t id0 = sid[a0 + pos];
-                    if (owner[id0] != kNone) continue;
-                    ++got;
-                    const float x0 = sx[a0 + pos], y0 = sy[a0 + pos], z0 = sz[a0 + pos];
-                    const float d01 = z1 - z0;
-                    const float tx = (x1 - x0) / d01;
-                    const float ty = (y1 - y0) / d01;
-                    const float dzc = Zc - z1;
-                    const uint16_t qe = phi16(x1 + tx * dzc, y1 + ty * dzc);
-                    if (nc == 0) continue;
-                    const uint16_t lo = (uint16_t)(qe - Ws);
-                    int st = lower_bound16(sq + c0, nc, lo);
-                    if (st == nc) st = 0;
-                    for (int j = 0; j < nc; ++j) {
-                        int pc = st + j;
-                        if (pc >= nc) pc -= nc;
-                        const uint16_t qc = sq[c0 + pc];
-                        if ((uint16_t)(qc - lo) > span) break;
-                        const uint16_t id2 = sid[c0 + pc];
-                        if (owner[id2] != kNone) continue;
-                        const float x2 = sx[c0 + pc], y2 = sy[c0 + pc], z2 = sz[c0 + pc];
-                        const float dz = z2 - z1;
-                        const float dx = (x1 + tx * dz) - x2;
-                        const float dy = (y1 + ty * dz) - y2;
-                        const float sc = (dx * dx) + (dy * dy);
-                        if (!(sc < Ss)) continue;
-                        if (!found || sc < bsc || (sc == bsc && (id0 < b0id || (id0 == b0id && id2 < b2id)))) {
-                            found = true;
-                            bsc = sc;
-                            b0id = id0; b2id = id2;
-                            x0b = x0; y0b = y0; z0b = z0;
-                            x2b = x2; y2b = y2; z2b = z2;
-                        }
-                    }
-                }
+    // unflagged positions of the doublet module and of the middle module, ascending
+    const int ga = hb + uni(S.mo[kmod(P, t - 2)]), gb = hb + uni(S.mo[kmod(P, t - 1)]);
+    uint16_t *F = na <= L.cap ? L.freel : W.freel + ga;
+    uint16_t *FR = na <= L.cap ? L.frank : W.frank + ga;
+    uint16_t *FM = nbm <= L.cap ? L.freem : W.freem + gb;
+    int nf = 0, nfm = 0;
+    const int nmax = na > nbm ? na : nbm;
+    for (int base = 0; base < nmax; base += B) {
+        const int p = base + (int)threadIdx.x;
+        const bool fa = p < na && is_free(own, wa.id[p]);
+        const bool fb = p < nbm && is_free(own, wb.id[p]);
+        int total;
+        const int idx = block_excl_scan<B>((fa ? 1 : 0) | (fb ? 0x10000 : 0), S.scan, &total);
+        if (p < na) FR[p] = (uint16_t)(nf + (idx & 0xFFFF));
+        if (fa) F[nf + (idx & 0xFFFF)] = (uint16_t)p;
+        if (fb) FM[nfm + (idx >> 16)] = (uint16_t)p;
+        nf += total & 0xFFFF;
+        nfm += total >> 16;
+    }
+    __syncthreads();
+    if (nf == 0 || nfm == 0) return;
+    const int hd = na >> 1, hu = na - hd - 1;   // offsets visited: [-hd, hu]
+    const int G = (K == 1 || K == 2 || K == 4 || K == 8 || K == 16) ? K : 1;
+    const int per_lane = G == 1 ? K : 1;
+
+    for (int base = 0; base < nfm * G; base += B) {
+        const int g = base + (int)threadIdx.x;
+        const int i = g / G, c = g - i * G;
+        SeedBest best;
+        best.found = false;
+        best.sc = 0.0f;
+        best.id0 = kNone;
+        best.id2 = kNone;
+        best.pos0 = 0;
+        best.pos2 = 0;
+        int p1 = 0;
+        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f;
+        if (i < nfm) {
+            p1 = FM[i];
+            x1 = wb.x[p1]; y1 = wb.y[p1]; z1 = wb.z[p1];
+            int s0 = lower_bound16(wa.q, na, wb.q[p1]);
+            if (s0 == na) s0 = 0;
+            const int j = FR[s0];   // first unflagged position >= s0, as an index into F
+            for (int cc = 0; cc < per_lane; ++cc) {
+                const int pos0 = pendulum_pick(F, nf, j, s0, na, hu, hd, c + cc);
+                if (pos0 < 0) break;
+                seed_doublet(wa, wc, own, pos0, x1, y1, z1, Zc, Ss, Ws, span, best);
             }
         }
-        const int r = wave_append(found, &S.cnt[0]);
-        const int l = wave_append(found, n_nxt);
-        if (found) {
+        // minimum over the G lanes of a middle hit
+        for (int m = 1; m < G; m <<= 1) {
+            SeedBest o;
+            o.found = __shfl_xor((int)best.found, m) != 0;
+            o.sc = __shfl_xor(best.sc, m);
+            o.id0 = (uint16_t)__shfl_xor((int)best.id0, m);
+            o.id2 = (uint16_t)__shfl_xor((int)best.id2, m);
+            o.pos0 = __shfl_xor(best.pos0, m);
+            o.pos2 = __shfl_xor(best.pos2, m);
+            if (seed_better(o, best)) best = o;
+        }
+        const bool emit = best.found && c == 0 && i < nfm;
+        const int r = wave_append(emit, &S.cnt[0]);
+        const int l = wave_append(emit, n_nxt);
+        if (emit) {
+            const float x0b = wa.x[best.pos0], y0b = wa.y[best.pos0], z0b = wa.z[best.pos0];
+            const float x2b = wc.x[best.pos2], y2b = wc.y[best.pos2], z2b = wc.z[best.pos2];
+            const uint16_t id1 = wb.id[p1];
             Rec R;
             const float d12 = z2b - z1;
             R.xb = x2b; R.yb = y2b; R.zb = z2b;
             R.tx = (x2b - x1) / d12;
             R.ty = (y2b - y1) / d12;
-            R.key = id1; R.h0 = b0id; R.h1 = id1; R.h2 = b2id; R.last = b2id;
+            R.key = id1; R.h0 = best.id0; R.h1 = id1; R.h2 = best.id2; R.last = best.id2;
             R.len = 3; R.last_t = (uint8_t)t;
             W.rec[hb + r] = R;
             // tracklet fit of the seed, hits in traversal order (Section 3,
@@ -424,129 +691,113 @@ __device__ void stage_seeding(const sbt_params &P, const HitsArgs &H, const Work
 // ---------------------------------------------------------------- following
 // Search against the flags at stage start, then claim (Section 3, "track
 // following"; conflicting claims resolved by minimum (scatter, key)).
+// rbest packs the best hit's id (low 16 bits) and its window position.
 template <int B>
-__device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
-                                    const uint16_t *act, int n_act)
+__device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, int t, const Shared<B> &S,
+                                    const Lds &L, const uint32_t *own, const uint16_t *act, int n_act)
 {
-    const int C = kmod(P, t);
-    const int c0 = S.mo[C], nc = S.mo[C + 1] - c0;
-    const float Zc = P.module_z[C];
+    const Win wc = window<B>(L, S, W, hb, t);
+    const int nc = wc.n;
+    const float Zc = P.module_z[kmod(P, t)];
     const float Sf = P.max_scatter_forwarding;
     const uint16_t Wf = (uint16_t)P.phi_window_forwarding;
     const uint16_t span = (uint16_t)(2 * P.phi_window_forwarding);
-    uint16_t *__restrict__ owner = W.owner + hb;
     unsigned long long *__restrict__ claim = W.claim + hb;
-    const float *sx = W.sx + hb, *sy = W.sy + hb, *sz = W.sz + hb;
-    const uint16_t *sq = W.sq + hb, *sid = W.sid + hb;
     for (int a = threadIdx.x; a < n_act; a += B) {
         const int r = act[a];
         const Rec R = W.rec[hb + r];
         uint16_t best = kNone;
+        int bpos = 0;
         float bsc = 0.0f;
-        uint8_t flag = 0;
         bool elig = (t - (int)R.last_t) <= P.max_consecutive_misses + 1;
         if (elig && R.len == 3)
-            elig = owner[R.h0] == kNone && owner[R.h1] == kNone && owner[R.h2] == kNone;
+            elig = is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2);
         if (elig && nc > 0) {
             const float dzc = Zc - R.zb;
             const uint16_t qe = phi16(R.xb + R.tx * dzc, R.yb + R.ty * dzc);
             const uint16_t lo = (uint16_t)(qe - Wf);
-            int st = lower_bound16(sq + c0, nc, lo);
+            int st = lower_bound16(wc.q, nc, lo);
             if (st == nc) st = 0;
             for (int j = 0; j < nc; ++j) {
                 int pc = st + j;
                 if (pc >= nc) pc -= nc;
-                const uint16_t qc = sq[c0 + pc];
+                const uint16_t qc = wc.q[pc];
                 if ((uint16_t)(qc - lo) > span) break;
-                const uint16_t id = sid[c0 + pc];
-                if (owner[id] != kNone) continue;
-                const float dz = sz[c0 + pc] - R.zb;
-                const float dx = (R.xb + R.tx * dz) - sx[c0 + pc];
-                const float dy = (R.yb + R.ty * dz) - sy[c0 + pc];
+                const uint16_t id = wc.id[pc];
+                if (!is_free(own, id)) continue;
+                const float dz = wc.z[pc] - R.zb;
+                const float dx = (R.xb + R.tx * dz) - wc.x[pc];
+                const float dy = (R.yb + R.ty * dz) - wc.y[pc];
                 const float sc = (dx * dx) + (dy * dy);
                 if (!(sc < Sf)) continue;
                 if (best == kNone || sc < bsc || (sc == bsc && id < best)) {
                     best = id;
+                    bpos = pc;
                     bsc = sc;
                 }
             }
             if (best != kNone) {
-                const unsigned long long kap = claim_key(bsc, R.key);
+                const unsigned long long kap = claim_key(bsc, R.key, t);
                 atomicMin(&claim[best], kap);
                 if (R.len == 3) {
                     atomicMin(&claim[R.h0], kap);
                     atomicMin(&claim[R.h1], kap);
                     atomicMin(&claim[R.h2], kap);
-                    flag = kFlagSeedClaim;
                 }
             }
         }
-        W.rbest[hb + r] = best;
+        W.rbest[hb + r] = best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
         W.rbsc[hb + r] = bsc;
-        W.rflag[hb + r] = flag;
     }
 }
 
 // A track wins iff its key is the minimum on every hit it claimed; winners
-// append their best hit and flag their claim set.
+// append their best hit and flag their claim set.  Tracks that have now missed
+// more than max_consecutive_misses modules in a row become final; the others
+// stay active for the next module.
 template <int B>
-__device__ void stage_follow_resolve(const HitsArgs &H, const Work &W, int hb, int t,
-                                     const uint16_t *act, int n_act)
+__device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
+                                     const Lds &L, uint32_t *own, const uint16_t *act, int n_act, uint16_t *nxt,
+                                     int *n_nxt)
 {
-    uint16_t *__restrict__ owner = W.owner + hb;
+    const Win wc = window<B>(L, S, W, hb, t);
     const unsigned long long *__restrict__ claim = W.claim + hb;
-    for (int a = threadIdx.x; a < n_act; a += B) {
-        const int r = act[a];
-        const uint16_t best = W.rbest[hb + r];
-        if (best == kNone) continue;
-        Rec R = W.rec[hb + r];
-        const unsigned long long kap = claim_key(W.rbsc[hb + r], R.key);
-        bool win = claim[best] == kap;
-        if (R.len == 3) win = win && claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap;
-        if (!win) continue;
-        owner[best] = R.key;
-        if (R.len == 3) {
-            owner[R.h0] = R.key;
-            owner[R.h1] = R.key;
-            owner[R.h2] = R.key;
-        }
-        W.prev[hb + best] = R.last;
-        const float xn = H.x[hb + best], yn = H.y[hb + best], zn = H.z[hb + best];
-        const float dab = zn - R.zb;
-        R.tx = (xn - R.xb) / dab;
-        R.ty = (yn - R.yb) / dab;
-        R.xb = xn; R.yb = yn; R.zb = zn;
-        R.last = best;
-        R.len = (uint8_t)(R.len + 1);
-        R.last_t = (uint8_t)t;
-        W.rec[hb + r] = R;
-    }
-}
-
-// Clears this stage's claims and moves tracks that missed too many modules
-// to the final list.
-template <int B>
-__device__ void stage_follow_cleanup(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
-                                     const uint16_t *act, int n_act, uint16_t *nxt, int *n_nxt)
-{
-    unsigned long long *__restrict__ claim = W.claim + hb;
     for (int base = 0; base < n_act; base += B) {
         const int a = base + (int)threadIdx.x;
         bool done = false, keep = false;
         int r = 0;
         if (a < n_act) {
             r = act[a];
-            const uint16_t best = W.rbest[hb + r];
-            const Rec R = W.rec[hb + r];
-            if (best != kNone) {
-                claim[best] = kNoClaim;
-                if (W.rflag[hb + r] & kFlagSeedClaim) {
-                    claim[R.h0] = kNoClaim;
-                    claim[R.h1] = kNoClaim;
-                    claim[R.h2] = kNoClaim;
+            const uint32_t pb = W.rbest[hb + r];
+            Rec R = W.rec[hb + r];
+            int last_t = R.last_t;
+            if (pb != 0xFFFFFFFFu) {
+                const uint16_t best = (uint16_t)(pb & 0xFFFF);
+                const int bpos = (int)(pb >> 16);
+                const unsigned long long kap = claim_key(W.rbsc[hb + r], R.key, t);
+                bool win = claim[best] == kap;
+                if (R.len == 3) win = win && claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap;
+                if (win) {
+                    set_flag(own, best);
+                    if (R.len == 3) {
+                        set_flag(own, R.h0);
+                        set_flag(own, R.h1);
+                        set_flag(own, R.h2);
+                    }
+                    W.prev[hb + best] = R.last;
+                    const float xn = wc.x[bpos], yn = wc.y[bpos], zn = wc.z[bpos];
+                    const float dab = zn - R.zb;
+                    R.tx = (xn - R.xb) / dab;
+                    R.ty = (yn - R.yb) / dab;
+                    R.xb = xn; R.yb = yn; R.zb = zn;
+                    R.last = best;
+                    R.len = (uint8_t)(R.len + 1);
+                    R.last_t = (uint8_t)t;
+                    W.rec[hb + r] = R;
+                    last_t = t;
                 }
             }
-            done = (t - (int)R.last_t) >= P.max_consecutive_misses + 1;
+            done = (t - last_t) >= P.max_consecutive_misses + 1;
             keep = !done;
         }
         const int f = wave_append(done, &S.cnt[3]);
@@ -556,45 +807,69 @@ __device__ void stage_follow_cleanup(const sbt_params &P, const Work &W, int hb,
     }
 }
 
+// The owner flags of an event: in LDS when the event fits, else in memory.
+__device__ __forceinline__ uint32_t *owner_words(const Work &W, int e, int hb) { return W.owner + (hb >> 5) + e; }
+
+__device__ __forceinline__ uint32_t *owner_ptr(const Lds &L, const Work &W, int e, int hb, int N)
+{
+    return N <= L.own_cap ? L.own : owner_words(W, e, hb);
+}
+
 // Seeding and following over all modules.  Leaves the final record list in
-// W.fin and its length in S.cnt[3].
+// W.fin and its length in S.cnt[3]; with writeback the owner flags are also
+// copied to memory.
 template <int B>
-__device__ void stage_track(const sbt_params &P, const HitsArgs &H, const Work &W, int hb, int N,
-                            Shared<B> &S)
+__device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S, const Lds &L,
+                            bool writeback)
 {
     const int M = P.n_modules;
+    uint32_t *own = owner_ptr(L, W, e, hb, N);
+    const int nw = (N + 31) >> 5;
+    for (int i = threadIdx.x; i < nw; i += B) own[i] = 0u;
     for (int i = threadIdx.x; i < N; i += B) {
-        W.owner[hb + i] = kNone;
         W.claim[hb + i] = kNoClaim;
         W.key2rec[hb + i] = kNone;
     }
     if (threadIdx.x == 0) {
         S.cnt[0] = 0; S.cnt[1] = 0; S.cnt[2] = 0; S.cnt[3] = 0;
     }
+    RingStage<B> R;
+    for (int u = 0; u < 3; ++u) {
+        ring_load<B>(P, W, hb, u, S, L, R);
+        ring_store<B>(P, W, hb, u, S, L, R);
+    }
     __syncthreads();
     uint16_t *const l0 = W.act0 + hb;
     uint16_t *const l1 = W.act1 + hb;
     int par = 0;
-    stage_seeding<B>(P, H, W, hb, 2, S, l0, &S.cnt[1]);
+    if (M > 3) ring_load<B>(P, W, hb, 3, S, L, R);
+    stage_seeding<B>(P, W, hb, 2, S, L, own, l0, &S.cnt[1]);
+    if (M > 3) ring_store<B>(P, W, hb, 3, S, L, R);
     __syncthreads();
     for (int t = 3; t < M; ++t) {
-        const int n_act = S.cnt[1 + par];
+        const int n_act = uni(S.cnt[1 + par]);
         const uint16_t *act = par ? l1 : l0;
         uint16_t *nxt = par ? l0 : l1;
         if (threadIdx.x == 0) S.cnt[1 + (par ^ 1)] = 0;
-        stage_follow_search<B>(P, W, hb, t, S, act, n_act);
+        stage_follow_search<B>(P, W, hb, t, S, L, own, act, n_act);
         __syncthreads();
-        stage_follow_resolve<B>(H, W, hb, t, act, n_act);
+        stage_follow_resolve<B>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
         __syncthreads();
-        stage_follow_cleanup<B>(P, W, hb, t, S, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
-        stage_seeding<B>(P, H, W, hb, t, S, nxt, &S.cnt[1 + (par ^ 1)]);
+        const bool more = t + 1 < M;
+        if (more) ring_load<B>(P, W, hb, t + 1, S, L, R);
+        stage_seeding<B>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)]);
+        if (more) ring_store<B>(P, W, hb, t + 1, S, L, R);
         __syncthreads();
         par ^= 1;
     }
-    const int n_act = S.cnt[1 + par];
-    const int nf = S.cnt[3];
+    const int n_act = uni(S.cnt[1 + par]);
+    const int nf = uni(S.cnt[3]);
     const uint16_t *act = par ? l1 : l0;
     for (int a = threadIdx.x; a < n_act; a += B) W.fin[hb + nf + a] = act[a];
+    if (writeback && N <= L.own_cap) {
+        uint32_t *g = owner_words(W, e, hb);
+        for (int i = threadIdx.x; i < nw; i += B) g[i] = own[i];
+    }
     __syncthreads();
     if (threadIdx.x == 0) S.cnt[3] = nf + n_act;
     __syncthreads();
@@ -605,10 +880,9 @@ __device__ void stage_track(const sbt_params &P, const HitsArgs &H, const Work &
 // fit chi2 is under the threshold and none of its hits is flagged; candidates
 // sharing hits keep the one with the minimum (chi2, key).
 template <int B>
-__device__ void stage_filter(const sbt_params &P, const Work &W, int hb, int n_fin)
+__device__ void stage_filter(const sbt_params &P, const Work &W, int hb, int n_fin, const uint32_t *own)
 {
     const float X = P.max_tracklet_chi2;
-    const uint16_t *__restrict__ owner = W.owner + hb;
     unsigned long long *__restrict__ claim = W.claim + hb;
     for (int a = threadIdx.x; a < n_fin; a += B) {
         const int r = W.fin[hb + a];
@@ -618,8 +892,8 @@ __device__ void stage_filter(const sbt_params &P, const Work &W, int hb, int n_f
             fl = kFlagAccepted;
         } else {
             const float c2 = W.rchi2[hb + r];
-            if (c2 < X && owner[R.h0] == kNone && owner[R.h1] == kNone && owner[R.h2] == kNone) {
-                const unsigned long long kap = claim_key(c2, R.key);
+            if (c2 < X && is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2)) {
+                const unsigned long long kap = claim_key(c2, R.key, kFilterStage);
                 atomicMin(&claim[R.h0], kap);
                 atomicMin(&claim[R.h1], kap);
                 atomicMin(&claim[R.h2], kap);
@@ -634,7 +908,7 @@ __device__ void stage_filter(const sbt_params &P, const Work &W, int hb, int n_f
         uint8_t fl = W.rflag[hb + r];
         const Rec R = W.rec[hb + r];
         if (fl == kFlagCandidate) {
-            const unsigned long long kap = claim_key(W.rchi2[hb + r], R.key);
+            const unsigned long long kap = claim_key(W.rchi2[hb + r], R.key, kFilterStage);
             fl = (claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap) ? kFlagAccepted : 0;
         }
         if (fl == kFlagAccepted) W.key2rec[hb + R.key] = (uint16_t)r;

@@ -70,11 +70,11 @@ class SbtTracks(ctypes.Structure):
 
 class SbtTuning(ctypes.Structure):
     _fields_ = [("threads_per_event", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("lds_window_hits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lds_window_hits", ctypes.c_int32), ("lds_owner_hits", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(threads_per_event=self.threads_per_event, blocks_per_cu=self.blocks_per_cu,
-                    lds_window_hits=self.lds_window_hits)
+                    lds_window_hits=self.lds_window_hits, lds_owner_hits=self.lds_owner_hits)
 
 
 class SbtServerConfig(ctypes.Structure):
@@ -163,12 +163,12 @@ def make_params(module_z, **overrides) -> SbtParams:
     return sp
 
 
-def make_tuning(threads_per_event=256, blocks_per_cu=4, lds_window_hits=0) -> SbtTuning:
+def make_tuning(threads_per_event=256, blocks_per_cu=3, lds_window_hits=672, lds_owner_hits=16384) -> SbtTuning:
     t = SbtTuning()
     t.threads_per_event = threads_per_event
     t.blocks_per_cu = blocks_per_cu
     t.lds_window_hits = lds_window_hits
-    t.reserved = 0
+    t.lds_owner_hits = lds_owner_hits
     return t
 
 

@@ -117,6 +117,21 @@ def test_batched_independent_of_launch_configuration(tpe, bpc):
     _same(got, want, f"tpe={tpe} bpc={bpc}")
 
 
+# LDS capacities: 0 or 1 forces every module window / the owner flags to be
+# read from memory, intermediate values mix both within one event
+LDS_CASES = [(0, 0), (1, 1), (64, 1000), (200, 3000), (672, 16384), (1024, 65536), (1536, 0)]
+
+
+@pytest.mark.parametrize("cap,own", LDS_CASES)
+@pytest.mark.parametrize("config,n", [("mu7.6", 16), ("mu30", 4)])
+def test_lds_overflow_fallbacks(cap, own, config, n):
+    say(f"lds cap={cap} own={own} {config} x{n}")
+    b = synth.make_batch(config, n, first=7)
+    want = oracle.reconstruct(b)
+    for tpe in (64, 256):
+        _same(run_batched(b, sbt.make_tuning(tpe, 2, cap, own)), want, f"cap={cap} own={own} tpe={tpe}")
+
+
 def test_random_tiny_events_and_parameters():
     """Crowded tiny events with random tolerances, traversal direction and
     miss allowance: the same events the oracle's brute-force pins use."""
