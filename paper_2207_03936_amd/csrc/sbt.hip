@@ -130,7 +130,7 @@ __global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work
         if (st == 0) {
             stage_sort<B>(P, H, W, hb, N, S, L);
             stage_track<B>(P, W, e, hb, N, S, L, false);
-            stage_filter<B>(P, W, hb, uni(S.cnt[3]), owner_ptr(L, W, e, hb, N));
+            stage_filter<B>(P, W, hb, uni(S.cnt[3]), owner_ptr<B>(S, L, W, e, hb, N));
             stage_compact<B>(W, e, hb, N, S.scan);
         } else if (threadIdx.x == 0) {
             W.ev_nt[e] = 0;

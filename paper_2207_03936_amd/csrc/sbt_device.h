@@ -262,15 +262,18 @@ struct Lds {
     uint16_t *freel;     // unflagged positions of the doublet module (cap entries)
     uint16_t *freem;     // unflagged positions of the middle module (cap entries)
     uint16_t *frank;     // unflagged positions before each doublet-module position
+    uint16_t *tab;       // per slot: first position whose phi16 high byte is >= b, b = 0..256
     uint32_t *own;
     int *hist, *fill;
 };
 
 __host__ __device__ __forceinline__ size_t lds_align(size_t v) { return (v + 15) & ~size_t(15); }
 
+constexpr int kTab = 257;
+
 __host__ __device__ __forceinline__ size_t lds_ring_bytes(int cap)
 {
-    return lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2);
+    return lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2) + lds_align((size_t)4 * kTab * 2);
 }
 
 __host__ __device__ __forceinline__ size_t lds_sort_head() { return lds_align((size_t)(2 * kSortBins + 1) * 4); }
@@ -298,6 +301,7 @@ __device__ __forceinline__ Lds carve_lds(char *base, int cap, int own_cap)
     L.freel = (uint16_t *)(base + lds_align((size_t)4 * cap * 16));
     L.freem = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + lds_align((size_t)cap * 2));
     L.frank = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 2 * lds_align((size_t)cap * 2));
+    L.tab = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2));
     L.own = (uint32_t *)(base + lds_ring_bytes(cap));
     L.hist = (int *)base;
     L.fill = L.hist + kSortBins + 1;
@@ -313,8 +317,7 @@ struct Shared {
     int e;
     int scan[B / 64 + 1];
     int slot_n[4];       // hits of the module held by each ring slot
-    int slot_g[4];       // its event-local offset
-    int slot_lds[4];     // 1: staged in LDS, 0: read from the sorted arrays in memory
+    int maxmod;          // hits of the event's largest module
 };
 
 // ---------------------------------------------------------------- validation
@@ -325,7 +328,10 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
 {
     const int M = P.n_modules;
     int lo = H.eo[e], hi = H.eo[e + 1];
-    if (threadIdx.x == 0) S.status = 0;
+    if (threadIdx.x == 0) {
+        S.status = 0;
+        S.maxmod = 0;
+    }
     __syncthreads();
     unsigned st = 0;
     if (lo < 0 || hi > H.n_hits || hi < lo) st = SBT_EV_BAD_OFFSETS;
@@ -338,6 +344,7 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
             bool bad = (k == 0 && v != lo) || (k == M && v != hi) || v < lo || v > hi;
             if (k > 0 && H.mo[base + k - 1] > v) bad = true;
             if (bad) atomicOr(&S.status, (int)SBT_EV_BAD_OFFSETS);
+            if (k < M) atomicMax(&S.maxmod, H.mo[base + k + 1] - v);
         }
     } else if (threadIdx.x == 0) {
         S.status = (int)st;
@@ -399,27 +406,50 @@ __device__ void stage_sort(const sbt_params &P, const HitsArgs &H, const Work &W
     __syncthreads();
 }
 
-// ---------------------------------------------------------------- module ring
-// Traversal index u lives in ring slot u & 3.  A module with more hits than a
-// slot holds is read from the sorted arrays in memory instead.
+// ---------------------------------------------------------------- module windows
+// An event whose modules all fit the LDS slots (and whose hit flags fit the
+// LDS bitmap) runs the LDS instantiation of the tracking stages: traversal
+// index u lives in ring slot u & 3 and every window access is an LDS access.
+// Any other event runs the memory instantiation, which reads the sorted
+// arrays in memory directly.  Both compute the same thing.
 struct Win {
     const uint16_t *q, *id;
     const float *x, *y, *z;
+    const uint16_t *tab;   // coarse index (LDS instantiation)
     int n;
 };
 
-template <int B>
-__device__ __forceinline__ Win window(const Lds &L, const Shared<B> &S, const Work &W, int hb, int u)
+// first position of the window whose phi16 is >= v
+template <bool kLds>
+__device__ __forceinline__ int win_lower_bound(const Win &w, uint16_t v)
 {
-    const int s = u & 3;
+    if (kLds) {
+        int p = w.tab[v >> 8];
+        const int end = w.tab[(v >> 8) + 1];
+        while (p < end && w.q[p] < v) ++p;
+        return p;
+    }
+    return lower_bound16(w.q, w.n, v);
+}
+
+template <int B, bool kLds>
+__device__ __forceinline__ Win window(const sbt_params &P, const Lds &L, const Shared<B> &S, const Work &W, int hb,
+                                      int u)
+{
     Win w;
-    w.n = uni(S.slot_n[s]);
-    if (uni(S.slot_lds[s])) {
+    if (kLds) {
+        const int s = u & 3;
         const int o = s * L.cap;
+        w.n = uni(S.slot_n[s]);
         w.q = L.rq + o; w.id = L.rid + o; w.x = L.rx + o; w.y = L.ry + o; w.z = L.rz + o;
+        w.tab = L.tab + s * kTab;
     } else {
-        const int g = hb + uni(S.slot_g[s]);
+        const int k = kmod(P, u);
+        const int g0 = uni(S.mo[k]);
+        w.n = uni(S.mo[k + 1]) - g0;
+        const int g = hb + g0;
         w.q = W.sq + g; w.id = W.sid + g; w.x = W.sx + g; w.y = W.sy + g; w.z = W.sz + g;
+        w.tab = nullptr;
     }
     return w;
 }
@@ -428,9 +458,22 @@ __device__ __forceinline__ Win window(const Lds &L, const Shared<B> &S, const Wo
 template <int B>
 struct RingStage {
     static constexpr int PF = (512 + B - 1) / B;
-    uint16_t q[PF], id[PF];
+    uint16_t q[PF], qp[PF], id[PF];
     float x[PF], y[PF], z[PF];
 };
+
+// coarse-index entries owned by position i of an n-hit slot whose phi16 is
+// q (qp: phi16 of position i-1): every high byte b with
+// high(qp) < b <= high(q) starts at i; the last position also closes the
+// table with n
+__device__ __forceinline__ void tab_fill(uint16_t *tab, int i, int n, uint16_t q, uint16_t qp)
+{
+    const int b_lo = i == 0 ? 0 : (qp >> 8) + 1;
+    const int b_hi = q >> 8;
+    for (int b = b_lo; b <= b_hi; ++b) tab[b] = (uint16_t)i;
+    if (i == n - 1)
+        for (int b = b_hi + 1; b < kTab; ++b) tab[b] = (uint16_t)n;
+}
 
 template <int B>
 __device__ __forceinline__ void ring_load(const sbt_params &P, const Work &W, int hb, int u, const Shared<B> &S,
@@ -438,12 +481,12 @@ __device__ __forceinline__ void ring_load(const sbt_params &P, const Work &W, in
 {
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
-    if (n > L.cap) return;
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
             R.q[j] = W.sq[hb + g + i];
+            R.qp[j] = i > 0 ? W.sq[hb + g + i - 1] : (uint16_t)0;
             R.id[j] = W.sid[hb + g + i];
             R.x[j] = W.sx[hb + g + i];
             R.y[j] = W.sy[hb + g + i];
@@ -459,14 +502,11 @@ __device__ __forceinline__ void ring_store(const sbt_params &P, const Work &W, i
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
     const int s = u & 3;
-    const bool lds = n <= L.cap;
-    if (threadIdx.x == 0) {
-        S.slot_n[s] = n;
-        S.slot_g[s] = g;
-        S.slot_lds[s] = lds ? 1 : 0;
-    }
-    if (!lds) return;
+    if (threadIdx.x == 0) S.slot_n[s] = n;
     const int o = s * L.cap;
+    uint16_t *tab = L.tab + s * kTab;
+    if (n == 0)
+        for (int b = threadIdx.x; b < kTab; b += B) tab[b] = 0;
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
@@ -476,14 +516,17 @@ __device__ __forceinline__ void ring_store(const sbt_params &P, const Work &W, i
             L.rx[o + i] = R.x[j];
             L.ry[o + i] = R.y[j];
             L.rz[o + i] = R.z[j];
+            tab_fill(tab, i, n, R.q[j], R.qp[j]);
         }
     }
     for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {
-        L.rq[o + i] = W.sq[hb + g + i];
+        const uint16_t q = W.sq[hb + g + i];
+        L.rq[o + i] = q;
         L.rid[o + i] = W.sid[hb + g + i];
         L.rx[o + i] = W.sx[hb + g + i];
         L.ry[o + i] = W.sy[hb + g + i];
         L.rz[o + i] = W.sz[hb + g + i];
+        tab_fill(tab, i, n, q, W.sq[hb + g + i - 1]);
     }
 }
 
@@ -542,6 +585,7 @@ __device__ __forceinline__ bool seed_better(const SeedBest &a, const SeedBest &b
     return a.id2 < b.id2;
 }
 
+template <bool kLds>
 __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const uint32_t *own, int pos0, float x1,
                                              float y1, float z1, float Zc, float Ss, uint16_t Ws, uint16_t span,
                                              SeedBest &b)
@@ -556,7 +600,7 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
     const int nc = wc.n;
     if (nc == 0) return;
     const uint16_t lo = (uint16_t)(qe - Ws);
-    int st = lower_bound16(wc.q, nc, lo);
+    int st = win_lower_bound<kLds>(wc, lo);
     if (st == nc) st = 0;
     for (int jj = 0; jj < nc; ++jj) {
         int pc = st + jj;
@@ -586,13 +630,13 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
 // K a power of two up to 16, the K doublets of a middle hit run on K adjacent
 // lanes and their best triplets are reduced with lane shuffles; otherwise
 // one lane handles all K doublets of its middle hit.
-template <int B>
+template <int B, bool kLds>
 __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
                               const uint32_t *own, uint16_t *nxt, int *n_nxt)
 {
-    const Win wa = window<B>(L, S, W, hb, t - 2);
-    const Win wb = window<B>(L, S, W, hb, t - 1);
-    const Win wc = window<B>(L, S, W, hb, t);
+    const Win wa = window<B, kLds>(P, L, S, W, hb, t - 2);
+    const Win wb = window<B, kLds>(P, L, S, W, hb, t - 1);
+    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
     const int na = wa.n, nbm = wb.n;
     const float Zc = P.module_z[kmod(P, t)];
     const float Ss = P.max_scatter_seeding;
@@ -601,10 +645,13 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
     const uint16_t span = (uint16_t)(2 * P.phi_window_seeding);
 
     // unflagged positions of the doublet module and of the middle module, ascending
-    const int ga = hb + uni(S.mo[kmod(P, t - 2)]), gb = hb + uni(S.mo[kmod(P, t - 1)]);
-    uint16_t *F = na <= L.cap ? L.freel : W.freel + ga;
-    uint16_t *FR = na <= L.cap ? L.frank : W.frank + ga;
-    uint16_t *FM = nbm <= L.cap ? L.freem : W.freem + gb;
+    uint16_t *F, *FR, *FM;
+    if (kLds) {
+        F = L.freel; FR = L.frank; FM = L.freem;
+    } else {
+        const int ga = hb + uni(S.mo[kmod(P, t - 2)]), gb = hb + uni(S.mo[kmod(P, t - 1)]);
+        F = W.freel + ga; FR = W.frank + ga; FM = W.freem + gb;
+    }
     int nf = 0, nfm = 0;
     const int nmax = na > nbm ? na : nbm;
     for (int base = 0; base < nmax; base += B) {
@@ -640,13 +687,13 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
         if (i < nfm) {
             p1 = FM[i];
             x1 = wb.x[p1]; y1 = wb.y[p1]; z1 = wb.z[p1];
-            int s0 = lower_bound16(wa.q, na, wb.q[p1]);
+            int s0 = win_lower_bound<kLds>(wa, wb.q[p1]);
             if (s0 == na) s0 = 0;
             const int j = FR[s0];   // first unflagged position >= s0, as an index into F
             for (int cc = 0; cc < per_lane; ++cc) {
                 const int pos0 = pendulum_pick(F, nf, j, s0, na, hu, hd, c + cc);
                 if (pos0 < 0) break;
-                seed_doublet(wa, wc, own, pos0, x1, y1, z1, Zc, Ss, Ws, span, best);
+                seed_doublet<kLds>(wa, wc, own, pos0, x1, y1, z1, Zc, Ss, Ws, span, best);
             }
         }
         // minimum over the G lanes of a middle hit
@@ -692,11 +739,11 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
 // Search against the flags at stage start, then claim (Section 3, "track
 // following"; conflicting claims resolved by minimum (scatter, key)).
 // rbest packs the best hit's id (low 16 bits) and its window position.
-template <int B>
+template <int B, bool kLds>
 __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, int t, const Shared<B> &S,
                                     const Lds &L, const uint32_t *own, const uint16_t *act, int n_act)
 {
-    const Win wc = window<B>(L, S, W, hb, t);
+    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
     const int nc = wc.n;
     const float Zc = P.module_z[kmod(P, t)];
     const float Sf = P.max_scatter_forwarding;
@@ -716,7 +763,7 @@ __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, 
             const float dzc = Zc - R.zb;
             const uint16_t qe = phi16(R.xb + R.tx * dzc, R.yb + R.ty * dzc);
             const uint16_t lo = (uint16_t)(qe - Wf);
-            int st = lower_bound16(wc.q, nc, lo);
+            int st = win_lower_bound<kLds>(wc, lo);
             if (st == nc) st = 0;
             for (int j = 0; j < nc; ++j) {
                 int pc = st + j;
@@ -755,12 +802,12 @@ __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, 
 // append their best hit and flag their claim set.  Tracks that have now missed
 // more than max_consecutive_misses modules in a row become final; the others
 // stay active for the next module.
-template <int B>
+template <int B, bool kLds>
 __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
                                      const Lds &L, uint32_t *own, const uint16_t *act, int n_act, uint16_t *nxt,
                                      int *n_nxt)
 {
-    const Win wc = window<B>(L, S, W, hb, t);
+    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
     const unsigned long long *__restrict__ claim = W.claim + hb;
     for (int base = 0; base < n_act; base += B) {
         const int a = base + (int)threadIdx.x;
@@ -810,20 +857,28 @@ __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb,
 // The owner flags of an event: in LDS when the event fits, else in memory.
 __device__ __forceinline__ uint32_t *owner_words(const Work &W, int e, int hb) { return W.owner + (hb >> 5) + e; }
 
-__device__ __forceinline__ uint32_t *owner_ptr(const Lds &L, const Work &W, int e, int hb, int N)
+// whether an event runs the LDS instantiation of the tracking stages
+template <int B>
+__device__ __forceinline__ bool event_in_lds(const Shared<B> &S, const Lds &L, int N)
 {
-    return N <= L.own_cap ? L.own : owner_words(W, e, hb);
+    return uni(S.maxmod) <= L.cap && N <= L.own_cap;
+}
+
+template <int B>
+__device__ __forceinline__ uint32_t *owner_ptr(const Shared<B> &S, const Lds &L, const Work &W, int e, int hb, int N)
+{
+    return event_in_lds<B>(S, L, N) ? L.own : owner_words(W, e, hb);
 }
 
 // Seeding and following over all modules.  Leaves the final record list in
 // W.fin and its length in S.cnt[3]; with writeback the owner flags are also
 // copied to memory.
-template <int B>
-__device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S, const Lds &L,
-                            bool writeback)
+template <int B, bool kLds>
+__device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S,
+                                 const Lds &L, bool writeback)
 {
     const int M = P.n_modules;
-    uint32_t *own = owner_ptr(L, W, e, hb, N);
+    uint32_t *own = kLds ? L.own : owner_words(W, e, hb);
     const int nw = (N + 31) >> 5;
     for (int i = threadIdx.x; i < nw; i += B) own[i] = 0u;
     for (int i = threadIdx.x; i < N; i += B) {
@@ -834,30 +889,31 @@ __device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, i
         S.cnt[0] = 0; S.cnt[1] = 0; S.cnt[2] = 0; S.cnt[3] = 0;
     }
     RingStage<B> R;
-    for (int u = 0; u < 3; ++u) {
-        ring_load<B>(P, W, hb, u, S, L, R);
-        ring_store<B>(P, W, hb, u, S, L, R);
-    }
+    if (kLds)
+        for (int u = 0; u < 3; ++u) {
+            ring_load<B>(P, W, hb, u, S, L, R);
+            ring_store<B>(P, W, hb, u, S, L, R);
+        }
     __syncthreads();
     uint16_t *const l0 = W.act0 + hb;
     uint16_t *const l1 = W.act1 + hb;
     int par = 0;
-    if (M > 3) ring_load<B>(P, W, hb, 3, S, L, R);
-    stage_seeding<B>(P, W, hb, 2, S, L, own, l0, &S.cnt[1]);
-    if (M > 3) ring_store<B>(P, W, hb, 3, S, L, R);
+    if (kLds && M > 3) ring_load<B>(P, W, hb, 3, S, L, R);
+    stage_seeding<B, kLds>(P, W, hb, 2, S, L, own, l0, &S.cnt[1]);
+    if (kLds && M > 3) ring_store<B>(P, W, hb, 3, S, L, R);
     __syncthreads();
     for (int t = 3; t < M; ++t) {
         const int n_act = uni(S.cnt[1 + par]);
         const uint16_t *act = par ? l1 : l0;
         uint16_t *nxt = par ? l0 : l1;
         if (threadIdx.x == 0) S.cnt[1 + (par ^ 1)] = 0;
-        stage_follow_search<B>(P, W, hb, t, S, L, own, act, n_act);
+        stage_follow_search<B, kLds>(P, W, hb, t, S, L, own, act, n_act);
         __syncthreads();
-        stage_follow_resolve<B>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
+        stage_follow_resolve<B, kLds>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
         __syncthreads();
-        const bool more = t + 1 < M;
+        const bool more = kLds && t + 1 < M;
         if (more) ring_load<B>(P, W, hb, t + 1, S, L, R);
-        stage_seeding<B>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)]);
+        stage_seeding<B, kLds>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)]);
         if (more) ring_store<B>(P, W, hb, t + 1, S, L, R);
         __syncthreads();
         par ^= 1;
@@ -866,13 +922,21 @@ __device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, i
     const int nf = uni(S.cnt[3]);
     const uint16_t *act = par ? l1 : l0;
     for (int a = threadIdx.x; a < n_act; a += B) W.fin[hb + nf + a] = act[a];
-    if (writeback && N <= L.own_cap) {
+    if (kLds && writeback) {
         uint32_t *g = owner_words(W, e, hb);
         for (int i = threadIdx.x; i < nw; i += B) g[i] = own[i];
     }
     __syncthreads();
     if (threadIdx.x == 0) S.cnt[3] = nf + n_act;
     __syncthreads();
+}
+
+template <int B>
+__device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S, const Lds &L,
+                            bool writeback)
+{
+    if (event_in_lds<B>(S, L, N)) stage_track_impl<B, true>(P, W, e, hb, N, S, L, writeback);
+    else stage_track_impl<B, false>(P, W, e, hb, N, S, L, writeback);
 }
 
 // ---------------------------------------------------------------- tracklet filter
