@@ -65,44 +65,20 @@ def measured_traffic(per_launch_hits: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def serving_leg(batch_pool, params, rate, seconds, budget_bytes):
-    """Poisson arrivals at `rate` events/s for `seconds`; returns latency
-    percentiles (ms) and the sustained rate."""
-    from paper_2207_03936_amd import sbt
-    srv = sbt.Server(params, device_budget_bytes=budget_bytes, n_slots=4, slot_events=512,
-                     slot_hits=1 << 21, max_wait_us=300)
-    rng = np.random.default_rng(123)
-    M = batch_pool.n_modules
-    E = batch_pool.n_events
-    n_total = int(rate * seconds)
-    gaps = rng.exponential(1.0 / rate, n_total)
-    arrivals = np.cumsum(gaps)
-    picks = rng.integers(0, E, n_total)
-    lat = []
-    t0 = sbt.sbt_now_us()
-    i = 0
-    done = 0
-    arrival_us = {}
-    while done < n_total:
-        now = (sbt.sbt_now_us() - t0) * 1e-6
-        while i < n_total and arrivals[i] <= now:
-            e = int(picks[i])
-            lo, hi = int(batch_pool.event_offsets[e]), int(batch_pool.event_offsets[e + 1])
-            mo = batch_pool.module_offsets[e * M:(e + 1) * M + 1] - lo
-            rc = srv.submit(i, mo, batch_pool.x[lo:hi], batch_pool.y[lo:hi], batch_pool.z[lo:hi])
-            if rc != 0:
-                break      # host queue full: retry on the next pass
-            arrival_us[i] = t0 + arrivals[i] * 1e6
-            i += 1
-        for (rid, st, tho, th, ts, td) in srv.poll(0):
-            lat.append(td - arrival_us.pop(rid))
-            done += 1
-    wall = (sbt.sbt_now_us() - t0) * 1e-6
+def serving_leg(params, seconds, fraction=0.5):
+    """Continuous-batching server fed by Poisson arrivals of events from the
+    mu ~ U{1..25} serving mixture: saturated throughput first, then latency
+    percentiles at `fraction` of it."""
+    from paper_2207_03936_amd import serve_bench, synth
+    pool = synth.make_batch("serve", 2000)
+    srv = serve_bench.make_server(params)
+    sat = serve_bench.run_rate(srv, pool, 0, 0, max_events=40_000)
+    rate = fraction * sat["sustained_events_per_s"]
+    res = serve_bench.run_rate(srv, pool, rate, seconds)
     srv.close()
-    lat = np.array(lat) * 1e-3
-    return dict(rate_per_s=rate, seconds=round(wall, 3), n_events=int(n_total),
-                sustained_events_per_s=round(n_total / wall, 1),
-                p50_ms=round(float(np.percentile(lat, 50)), 4), p99_ms=round(float(np.percentile(lat, 99)), 4))
+    res["saturation_events_per_s"] = sat["sustained_events_per_s"]
+    res["workload"] = "Poisson arrivals of mu ~ U{1..25} events (pool of 2,000, seed 5)"
+    return res
 
 
 def cpu_baseline(batch, gpu_out, target_s=12.0):
@@ -141,6 +117,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--tpe", type=int, default=0, help="threads per event (0: autotune)")
     ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (0: autotune)")
+    ap.add_argument("--cap", type=int, default=672, help="LDS slot capacity in hits (with --tpe/--bpc)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so "
@@ -160,7 +139,7 @@ def main():
     ws = sbt.Workspace(E, H)
     ctx = sbt.Context(params, E, H)
     if args.tpe and args.bpc:
-        ctx.set_tuning(sbt.make_tuning(args.tpe, args.bpc))
+        ctx.set_tuning(sbt.make_tuning(args.tpe, args.bpc, args.cap))
         tuned_ms = None
     else:
         best, tuned_ms = ctx.autotune(dev, reps=3)
@@ -231,13 +210,18 @@ def main():
     if tuned_ms is not None:
         result["autotune_ms"] = round(tuned_ms, 4)
     if not args.no_serve:
-        cap = E / sec_batched
-        pool = synth.make_batch("mu1-25", 2000)
-        result["serving"] = serving_leg(pool, params, rate=min(0.5 * cap, 20000.0),
-                                        seconds=args.serve_seconds, budget_bytes=8 << 30)
+        result["serving"] = serving_leg(params, args.serve_seconds)
         result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(batch, got)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)     # one elementwise kernel: reads and writes 4n bytes
+        torch.cuda.synchronize()
+        result["calibration_copy_bytes"] = 4 * n
     ctx.close()
     print(json.dumps(result), flush=True)
 

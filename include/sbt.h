@@ -287,6 +287,19 @@ int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits,
 int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_results,
                     int32_t wait_us);
 
+/* Load replay, for measuring the server.  Arrival i (0..n_arrivals-1) is
+ * event picks[i] of a packed HOST pool (pool_events events; event_offsets
+ * [pool_events+1], module_offsets [pool_events*M+1] absolute, x/y/z); it is
+ * submitted at start + arrival_us[i] (microseconds, non-decreasing) while the
+ * server is polled continuously, its hits read in place (the pool must stay
+ * unchanged during the call).  Writes each arrival's latency (result visible
+ * on the host minus its arrival time) into latency_us[i], its track count
+ * into n_tracks[i] (may be NULL), and the wall time into *wall_us.      */
+int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival_us, const int32_t *picks,
+                      int32_t pool_events, const int32_t *event_offsets, const int32_t *module_offsets,
+                      const float *x, const float *y, const float *z,
+                      double *latency_us, int32_t *n_tracks, double *wall_us);
+
 /* Events queued on the host, and events on the device. */
 int sbt_server_pending(const sbt_server *srv, int32_t *queued, int32_t *in_flight);
 

@@ -40,7 +40,8 @@ struct QueuedEvent {
     int64_t id;
     double t_submit;
     std::vector<int32_t> mo;   // M+1 local offsets
-    std::vector<float> xyz;    // x[n], y[n], z[n]
+    std::vector<float> xyz;    // x[n], y[n], z[n] (owned copy)
+    const float *bx, *by, *bz; // borrowed hits (load replay), or null
     int32_t n;
 };
 
@@ -176,9 +177,12 @@ void pack(sbt_server *srv, Slot &s, const QueuedEvent &q)
         s.t_oldest = q.t_submit;
     }
     const int32_t base = s.n_hits;
-    memcpy(s.hx + base, q.xyz.data(), sizeof(float) * q.n);
-    memcpy(s.hy + base, q.xyz.data() + q.n, sizeof(float) * q.n);
-    memcpy(s.hz + base, q.xyz.data() + 2 * (size_t)q.n, sizeof(float) * q.n);
+    const float *qx = q.bx ? q.bx : q.xyz.data();
+    const float *qy = q.bx ? q.by : q.xyz.data() + q.n;
+    const float *qz = q.bx ? q.bz : q.xyz.data() + 2 * (size_t)q.n;
+    memcpy(s.hx + base, qx, sizeof(float) * q.n);
+    memcpy(s.hy + base, qy, sizeof(float) * q.n);
+    memcpy(s.hz + base, qz, sizeof(float) * q.n);
     for (int k = 1; k <= M; ++k) s.hmo[(size_t)s.n_events * M + k] = base + q.mo[k];
     s.n_hits += q.n;
     s.n_events += 1;
@@ -362,6 +366,7 @@ int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits, const
     QueuedEvent q;
     q.id = request_id;
     q.t_submit = now_us();
+    q.bx = q.by = q.bz = nullptr;
     q.n = n_hits;
     q.mo.assign(module_offsets, module_offsets + M + 1);
     q.xyz.resize(3 * (size_t)n_hits);
@@ -398,6 +403,51 @@ int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_res
         results[i].track_hits = srv->store[(size_t)i].th.data();
     }
     return n;
+}
+
+int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival_us, const int32_t *picks,
+                      int32_t pool_events, const int32_t *event_offsets, const int32_t *module_offsets,
+                      const float *x, const float *y, const float *z, double *latency_us, int32_t *n_tracks,
+                      double *wall_us)
+{
+    if (!srv || n_arrivals < 0 || pool_events < 1 || !arrival_us || !picks || !event_offsets || !module_offsets ||
+        !x || !y || !z || !latency_us || !wall_us)
+        return SBT_ERR_INVALID_ARG;
+    const int M = srv->params.n_modules;
+    for (int32_t i = 0; i < n_arrivals; ++i)
+        if (picks[i] < 0 || picks[i] >= pool_events) return SBT_ERR_INVALID_ARG;
+    std::vector<sbt_server_result> res(512);
+    const double t0 = now_us();
+    int32_t next = 0, done = 0;
+    while (done < n_arrivals) {
+        const double t = now_us() - t0;
+        while (next < n_arrivals && arrival_us[next] <= t && srv->queue.size() < srv->max_queue) {
+            const int32_t e = picks[next];
+            const int32_t lo = event_offsets[e], hi = event_offsets[e + 1];
+            if (hi - lo > SBT_MAX_EVENT_HITS || hi < lo) return SBT_ERR_EVENT_TOO_LARGE;
+            QueuedEvent q;
+            q.id = next;
+            q.t_submit = t0 + arrival_us[next];
+            q.n = hi - lo;
+            q.mo.resize((size_t)M + 1);
+            for (int k = 0; k <= M; ++k) q.mo[(size_t)k] = module_offsets[(size_t)e * M + k] - lo;
+            q.bx = x + lo;
+            q.by = y + lo;
+            q.bz = z + lo;
+            srv->queue.push_back(std::move(q));
+            ++next;
+        }
+        int n = sbt_server_poll(srv, res.data(), (int32_t)res.size(), 0);
+        if (n < 0) return n;
+        for (int i = 0; i < n; ++i) {
+            const int64_t id = res[(size_t)i].request_id;
+            latency_us[id] = res[(size_t)i].t_done_us - (t0 + arrival_us[id]);
+            if (n_tracks) n_tracks[id] = res[(size_t)i].n_tracks;
+            ++done;
+        }
+    }
+    *wall_us = now_us() - t0;
+    return SBT_OK;
 }
 
 int sbt_server_pending(const sbt_server *srv, int32_t *queued, int32_t *in_flight)

@@ -116,6 +116,10 @@ PROTOTYPES = {
                                          _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float)]),
     "sbt_server_poll": (ctypes.c_int, [_VP, _P(SbtServerResult), ctypes.c_int32, ctypes.c_int32]),
     "sbt_server_pending": (ctypes.c_int, [_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "sbt_server_replay": (ctypes.c_int, [_VP, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int32),
+                                         ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                         _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float),
+                                         _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "sbt_now_us": (ctypes.c_double, []),
 }
 
@@ -400,6 +404,32 @@ class Server:
                   if tho[-1] > 0 else np.zeros(0, np.int32))
             out.append((int(r.request_id), int(r.status), tho, th, float(r.t_submit_us), float(r.t_done_us)))
         return out
+
+    def replay(self, pool, arrival_us, picks):
+        """Arrival i is event picks[i] of the host batch `pool`, submitted at
+        arrival_us[i] (us from the start); returns (latency_us, n_tracks,
+        wall_us)."""
+        arr = np.ascontiguousarray(arrival_us, dtype=np.float64)
+        pk = np.ascontiguousarray(picks, dtype=np.int32)
+        assert arr.size == pk.size
+        n = int(arr.size)
+        E = int(pool.event_offsets.shape[0] - 1)
+        eo = np.ascontiguousarray(pool.event_offsets, dtype=np.int32)
+        mo = np.ascontiguousarray(pool.module_offsets, dtype=np.int32)
+        x = np.ascontiguousarray(pool.x, dtype=np.float32)
+        y = np.ascontiguousarray(pool.y, dtype=np.float32)
+        z = np.ascontiguousarray(pool.z, dtype=np.float32)
+        lat = np.zeros(n, np.float64)
+        nt = np.zeros(n, np.int32)
+        wall = ctypes.c_double(0)
+        P = ctypes.POINTER
+        _check(lib().sbt_server_replay(self.handle, n, arr.ctypes.data_as(P(ctypes.c_double)),
+                                       pk.ctypes.data_as(P(ctypes.c_int32)), E,
+                                       eo.ctypes.data_as(P(ctypes.c_int32)), mo.ctypes.data_as(P(ctypes.c_int32)),
+                                       x.ctypes.data_as(P(ctypes.c_float)), y.ctypes.data_as(P(ctypes.c_float)),
+                                       z.ctypes.data_as(P(ctypes.c_float)), lat.ctypes.data_as(P(ctypes.c_double)),
+                                       nt.ctypes.data_as(P(ctypes.c_int32)), ctypes.byref(wall)), "sbt_server_replay")
+        return lat, nt, float(wall.value)
 
     def pending(self):
         q, f = ctypes.c_int32(0), ctypes.c_int32(0)

@@ -1,0 +1,83 @@
+"""Serving measurement: Poisson arrivals into the continuous-batching server.
+
+Events are drawn from the serving recipe (per-event pileup mu ~ U{1..25},
+seed 5) into a pool of distinct events; arrival i is a uniformly chosen pool
+event submitted at its Poisson arrival time by the library's replay driver,
+which polls the server continuously.  Latency is the time from an event's
+arrival to its tracks being visible on the host (queueing, H2D copy,
+reconstruction, D2H copy and collection included).
+
+    python -m paper_2207_03936_amd.serve_bench --rates 0.25,0.5,0.8,0.95 --seconds 60
+
+Rates are fractions of the saturated throughput measured first (every
+arrival at time zero), or absolute events/s when larger than 1.  Prints one
+JSON line per rate.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import sbt, synth
+
+
+def make_server(params, budget_bytes=8 << 30, n_slots=4, slot_events=512, slot_hits=1 << 21, max_wait_us=300,
+                tuning=None):
+    return sbt.Server(params, device_budget_bytes=budget_bytes, n_slots=n_slots, slot_events=slot_events,
+                      slot_hits=slot_hits, max_wait_us=max_wait_us, tuning=tuning)
+
+
+def run_rate(srv, pool, rate, seconds, seed=123, max_events=2_000_000):
+    """Replay Poisson arrivals at `rate` events/s for `seconds` (rate <= 0:
+    all arrivals at time zero).  Returns a dict of latency percentiles and
+    sustained throughput."""
+    rng = np.random.default_rng(seed)
+    n = int(min(max_events, max(1, rate * seconds))) if rate > 0 else int(max_events)
+    arrivals = np.cumsum(rng.exponential(1e6 / rate, n)) if rate > 0 else np.zeros(n)
+    picks = rng.integers(0, pool.n_events, n).astype(np.int32)
+    lat, nt, wall = srv.replay(pool, arrivals, picks)
+    hits = int(np.diff(pool.event_offsets)[picks].sum())
+    lat_ms = lat * 1e-3
+    return dict(rate_per_s=round(float(rate), 1), n_events=n, seconds=round(wall * 1e-6, 3),
+                sustained_events_per_s=round(n / (wall * 1e-6), 1),
+                sustained_hits_per_s=round(hits / (wall * 1e-6), 1),
+                p50_ms=round(float(np.percentile(lat_ms, 50)), 4),
+                p99_ms=round(float(np.percentile(lat_ms, 99)), 4),
+                max_ms=round(float(lat_ms.max()), 4), n_tracks=int(nt.sum()))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--rates", default="0.25,0.5,0.8,0.95")
+    ap.add_argument("--seconds", type=float, default=60.0)
+    ap.add_argument("--pool", type=int, default=4000)
+    ap.add_argument("--saturation-events", type=int, default=100_000)
+    ap.add_argument("--budget-gib", type=float, default=8.0)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slot-events", type=int, default=512)
+    ap.add_argument("--slot-hits", type=int, default=1 << 21)
+    ap.add_argument("--max-wait-us", type=int, default=300)
+    args = ap.parse_args(argv)
+    import torch
+    assert torch.cuda.is_available(), "serving needs a GPU"
+    pool = synth.make_batch("serve", args.pool)
+    params = sbt.make_params(pool.module_z)
+    srv = make_server(params, int(args.budget_gib * (1 << 30)), args.slots, args.slot_events, args.slot_hits,
+                      args.max_wait_us)
+    sat = run_rate(srv, pool, 0, 0, max_events=args.saturation_events)
+    cap = sat["sustained_events_per_s"]
+    print(json.dumps(dict(kind="saturation", config=vars(args), **sat)), flush=True)
+    for r in args.rates.split(","):
+        r = float(r)
+        rate = r * cap if r <= 1.0 else r
+        res = run_rate(srv, pool, rate, args.seconds)
+        print(json.dumps(dict(kind="poisson", fraction_of_saturation=round(rate / cap, 4), **res)), flush=True)
+    srv.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())
