@@ -223,3 +223,19 @@ def test_chi2_collinear_is_zero_and_scatter_identity():
         v = np.array([zf[2] - zf[1], zf[0] - zf[2], zf[1] - zf[0]])
         want = (dx * dx + dy * dy) * (zf[1] - zf[0]) ** 2 / (v @ v)
         assert oracle.tracklet_chi2(x, y, z) == pytest.approx(want, rel=1e-3, abs=1e-6)
+
+
+def test_phi16_coefficients_follow_their_derivation():
+    """The oracle's polynomial literals are the binary32 rounding of the
+    float64 fit in oracle/derive_phi16.py, and that fit's binary32 error is
+    within 0.15 phi16 units."""
+    import re
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle"))
+    import derive_phi16
+    c = derive_phi16.fit()
+    src = open(os.path.join(os.path.dirname(os.path.dirname(__file__)), "oracle", "sbt_oracle.c")).read()
+    lits = [float.fromhex(m) for m in re.findall(r"ORC_C\d = (-?0x[0-9a-f.p+-]+)f;", src)]
+    assert len(lits) == 5
+    assert [float(v) for v in c] == lits
+    assert derive_phi16.max_error(c) * 32768 / np.pi < 0.15
