@@ -118,6 +118,16 @@ __device__ __forceinline__ uint16_t phi16(float x, float y)
 }
 
 // ---------------------------------------------------------------- small helpers
+// Workgroup barrier that orders LDS accesses only: stores to memory issued
+// before it are not waited for.  Used where the next phase reads nothing the
+// previous one wrote to memory.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // A value every lane of the wave holds alike (read from LDS, for instance),
 // moved to a scalar register.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -203,7 +213,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_w, int *total)
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int inc = wave_inclusive_scan(v);
     if (lane == 63) s_w[w] = inc;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         int acc = 0;
         for (int i = 0; i < B / 64; ++i) {
@@ -213,10 +223,10 @@ __device__ __forceinline__ int block_excl_scan(int v, int *s_w, int *total)
         }
         s_w[B / 64] = acc;
     }
-    __syncthreads();
+    lds_barrier();
     int r = s_w[w] + inc - v;
     *total = s_w[B / 64];
-    __syncthreads();
+    lds_barrier();
     return r;
 }
 
@@ -253,6 +263,9 @@ __host__ __device__ __forceinline__ int sort_shift(int M)
 //   ring  4 slots x cap hits: phi16, id, x, y, z (16 B per hit)
 //   freel unflagged positions of the seeding stage's doublet module
 //   frank rank of each doublet-module position among its unflagged positions
+//   tab   coarse phi index of each slot
+//   al0/al1, sbest, sbsc  active-track lists and per-stage search results of
+//         the first cap active tracks (the rest live in memory)
 //   own   hit-flag bitmap of the event when N <= own_cap
 struct Lds {
     int cap, own_cap, sortcap;
@@ -263,6 +276,9 @@ struct Lds {
     uint16_t *freem;     // unflagged positions of the middle module (cap entries)
     uint16_t *frank;     // unflagged positions before each doublet-module position
     uint16_t *tab;       // per slot: first position whose phi16 high byte is >= b, b = 0..256
+    uint16_t *al0, *al1; // active track lists (first cap entries)
+    uint32_t *sbest;     // per active slot: best hit id | window position << 16
+    float *sbsc;         // per active slot: its scatter
     uint32_t *own;
     int *hist, *fill;
 };
@@ -273,7 +289,8 @@ constexpr int kTab = 257;
 
 __host__ __device__ __forceinline__ size_t lds_ring_bytes(int cap)
 {
-    return lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2) + lds_align((size_t)4 * kTab * 2);
+    return lds_align((size_t)4 * cap * 16) + 5 * lds_align((size_t)cap * 2) + lds_align((size_t)4 * kTab * 2) +
+           2 * lds_align((size_t)cap * 4);
 }
 
 __host__ __device__ __forceinline__ size_t lds_sort_head() { return lds_align((size_t)(2 * kSortBins + 1) * 4); }
@@ -301,7 +318,16 @@ __device__ __forceinline__ Lds carve_lds(char *base, int cap, int own_cap)
     L.freel = (uint16_t *)(base + lds_align((size_t)4 * cap * 16));
     L.freem = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + lds_align((size_t)cap * 2));
     L.frank = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 2 * lds_align((size_t)cap * 2));
-    L.tab = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2));
+    char *p = base + lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2);
+    L.tab = (uint16_t *)p;
+    p += lds_align((size_t)4 * kTab * 2);
+    L.al0 = (uint16_t *)p;
+    p += lds_align((size_t)cap * 2);
+    L.al1 = (uint16_t *)p;
+    p += lds_align((size_t)cap * 2);
+    L.sbest = (uint32_t *)p;
+    p += lds_align((size_t)cap * 4);
+    L.sbsc = (float *)p;
     L.own = (uint32_t *)(base + lds_ring_bytes(cap));
     L.hist = (int *)base;
     L.fill = L.hist + kSortBins + 1;
@@ -530,6 +556,20 @@ __device__ __forceinline__ void ring_store(const sbt_params &P, const Work &W, i
     }
 }
 
+// ---------------------------------------------------------------- active lists
+// A list of record indices whose first cap entries live in LDS and the rest
+// in memory (cap = 0 in the memory instantiation).
+struct AList {
+    uint16_t *lds, *mem;
+    int cap;
+    __device__ __forceinline__ uint16_t get(int a) const { return a < cap ? lds[a] : mem[a]; }
+    __device__ __forceinline__ void put(int a, uint16_t v) const
+    {
+        if (a < cap) lds[a] = v;
+        else mem[a] = v;
+    }
+};
+
 // ---------------------------------------------------------------- seeding
 // Seeding(t), t >= 2 (Section 3): modules A = kmod(t-2), Bm = kmod(t-1),
 // C = kmod(t).  One lane per middle hit of Bm.
@@ -632,7 +672,7 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
 // one lane handles all K doublets of its middle hit.
 template <int B, bool kLds>
 __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
-                              const uint32_t *own, uint16_t *nxt, int *n_nxt)
+                              const uint32_t *own, const AList &nxt, int *n_nxt)
 {
     const Win wa = window<B, kLds>(P, L, S, W, hb, t - 2);
     const Win wb = window<B, kLds>(P, L, S, W, hb, t - 1);
@@ -666,7 +706,9 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
         nf += total & 0xFFFF;
         nfm += total >> 16;
     }
-    __syncthreads();
+    // the lists are in LDS in the LDS instantiation, in memory otherwise
+    if (kLds) lds_barrier();
+    else __syncthreads();
     if (nf == 0 || nfm == 0) return;
     const int hd = na >> 1, hu = na - hd - 1;   // offsets visited: [-hd, hu]
     const int G = (K == 1 || K == 2 || K == 4 || K == 8 || K == 16) ? K : 1;
@@ -730,7 +772,7 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
             const float ssy = ((v0 * y0b) + (v1 * y1)) + (v2 * y2b);
             const float n2 = ((v0 * v0) + (v1 * v1)) + (v2 * v2);
             W.rchi2[hb + r] = ((ssx * ssx) + (ssy * ssy)) / n2;
-            nxt[l] = (uint16_t)r;
+            nxt.put(l, (uint16_t)r);
         }
     }
 }
@@ -741,7 +783,7 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
 // rbest packs the best hit's id (low 16 bits) and its window position.
 template <int B, bool kLds>
 __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, int t, const Shared<B> &S,
-                                    const Lds &L, const uint32_t *own, const uint16_t *act, int n_act)
+                                    const Lds &L, const uint32_t *own, const AList &act, int n_act)
 {
     const Win wc = window<B, kLds>(P, L, S, W, hb, t);
     const int nc = wc.n;
@@ -751,7 +793,7 @@ __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, 
     const uint16_t span = (uint16_t)(2 * P.phi_window_forwarding);
     unsigned long long *__restrict__ claim = W.claim + hb;
     for (int a = threadIdx.x; a < n_act; a += B) {
-        const int r = act[a];
+        const int r = act.get(a);
         const Rec R = W.rec[hb + r];
         uint16_t best = kNone;
         int bpos = 0;
@@ -793,8 +835,14 @@ __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, 
                 }
             }
         }
-        W.rbest[hb + r] = best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
-        W.rbsc[hb + r] = bsc;
+        const uint32_t pb = best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
+        if (a < act.cap) {
+            L.sbest[a] = pb;
+            L.sbsc[a] = bsc;
+        } else {
+            W.rbest[hb + r] = pb;
+            W.rbsc[hb + r] = bsc;
+        }
     }
 }
 
@@ -804,7 +852,7 @@ __device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, 
 // stay active for the next module.
 template <int B, bool kLds>
 __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
-                                     const Lds &L, uint32_t *own, const uint16_t *act, int n_act, uint16_t *nxt,
+                                     const Lds &L, uint32_t *own, const AList &act, int n_act, const AList &nxt,
                                      int *n_nxt)
 {
     const Win wc = window<B, kLds>(P, L, S, W, hb, t);
@@ -814,14 +862,15 @@ __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb,
         bool done = false, keep = false;
         int r = 0;
         if (a < n_act) {
-            r = act[a];
-            const uint32_t pb = W.rbest[hb + r];
+            r = act.get(a);
+            const bool in_lds = a < act.cap;
+            const uint32_t pb = in_lds ? L.sbest[a] : W.rbest[hb + r];
             Rec R = W.rec[hb + r];
             int last_t = R.last_t;
             if (pb != 0xFFFFFFFFu) {
                 const uint16_t best = (uint16_t)(pb & 0xFFFF);
                 const int bpos = (int)(pb >> 16);
-                const unsigned long long kap = claim_key(W.rbsc[hb + r], R.key, t);
+                const unsigned long long kap = claim_key(in_lds ? L.sbsc[a] : W.rbsc[hb + r], R.key, t);
                 bool win = claim[best] == kap;
                 if (R.len == 3) win = win && claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap;
                 if (win) {
@@ -850,7 +899,7 @@ __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb,
         const int f = wave_append(done, &S.cnt[3]);
         if (done) W.fin[hb + f] = (uint16_t)r;
         const int l = wave_append(keep, n_nxt);
-        if (keep) nxt[l] = (uint16_t)r;
+        if (keep) nxt.put(l, (uint16_t)r);
     }
 }
 
@@ -895,8 +944,8 @@ __device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int 
             ring_store<B>(P, W, hb, u, S, L, R);
         }
     __syncthreads();
-    uint16_t *const l0 = W.act0 + hb;
-    uint16_t *const l1 = W.act1 + hb;
+    const AList l0 = {kLds ? L.al0 : nullptr, W.act0 + hb, kLds ? L.cap : 0};
+    const AList l1 = {kLds ? L.al1 : nullptr, W.act1 + hb, kLds ? L.cap : 0};
     int par = 0;
     if (kLds && M > 3) ring_load<B>(P, W, hb, 3, S, L, R);
     stage_seeding<B, kLds>(P, W, hb, 2, S, L, own, l0, &S.cnt[1]);
@@ -904,13 +953,16 @@ __device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int 
     __syncthreads();
     for (int t = 3; t < M; ++t) {
         const int n_act = uni(S.cnt[1 + par]);
-        const uint16_t *act = par ? l1 : l0;
-        uint16_t *nxt = par ? l0 : l1;
+        const AList &act = par ? l1 : l0;
+        const AList &nxt = par ? l0 : l1;
         if (threadIdx.x == 0) S.cnt[1 + (par ^ 1)] = 0;
         stage_follow_search<B, kLds>(P, W, hb, t, S, L, own, act, n_act);
         __syncthreads();
         stage_follow_resolve<B, kLds>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
-        __syncthreads();
+        // seeding reads only LDS state written so far (flags, slots, lists);
+        // with the flags in memory the full barrier is needed
+        if (kLds) lds_barrier();
+        else __syncthreads();
         const bool more = kLds && t + 1 < M;
         if (more) ring_load<B>(P, W, hb, t + 1, S, L, R);
         stage_seeding<B, kLds>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)]);
@@ -920,8 +972,8 @@ __device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int 
     }
     const int n_act = uni(S.cnt[1 + par]);
     const int nf = uni(S.cnt[3]);
-    const uint16_t *act = par ? l1 : l0;
-    for (int a = threadIdx.x; a < n_act; a += B) W.fin[hb + nf + a] = act[a];
+    const AList &act = par ? l1 : l0;
+    for (int a = threadIdx.x; a < n_act; a += B) W.fin[hb + nf + a] = act.get(a);
     if (kLds && writeback) {
         uint32_t *g = owner_words(W, e, hb);
         for (int i = threadIdx.x; i < nw; i += B) g[i] = own[i];
