@@ -571,8 +571,6 @@ struct AList {
 };
 
 // ---------------------------------------------------------------- seeding
-// Seeding(t), t >= 2 (Section 3): modules A = kmod(t-2), Bm = kmod(t-1),
-// C = kmod(t).  One lane per middle hit of Bm.
 // The pendulum search visits the doublet module's phi-sorted positions in
 // the order s0, s0-1, s0+1, s0-2, s0+2, ... (wrapping, at most n visits) and
 // keeps the first K unflagged ones.  Here the unflagged positions are first
@@ -665,18 +663,100 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
     }
 }
 
-// Seeding(t), t >= 2 (Section 3): modules A = kmod(t-2), Bm = kmod(t-1),
-// C = kmod(t).  Work items are (unflagged middle hit, partner rank c): with
-// K a power of two up to 16, the K doublets of a middle hit run on K adjacent
-// lanes and their best triplets are reduced with lane shuffles; otherwise
-// one lane handles all K doublets of its middle hit.
+// ---------------------------------------------------------------- following search
+// Following search of one forming track into traversal index u (Section 3,
+// "track following"): the last two hits extrapolated to the module's
+// nominal z, the best unflagged hit of the inclusive phi window by
+// (scatter, id) under the threshold, and claims on that hit (and on the
+// three seed hits of a bare seed) keyed (scatter, key) for stage u.
+// Returns the best hit's id | window position << 16, or ~0.
+template <bool kLds>
+__device__ __forceinline__ uint32_t follow_item(const sbt_params &P, const Win &wc, float Zc, const uint32_t *own,
+                                                unsigned long long *claim, const Rec &R, int u, float &bsc_out)
+{
+    const float Sf = P.max_scatter_forwarding;
+    const uint16_t Wf = (uint16_t)P.phi_window_forwarding;
+    const uint16_t span = (uint16_t)(2 * P.phi_window_forwarding);
+    const int nc = wc.n;
+    uint16_t best = kNone;
+    int bpos = 0;
+    float bsc = 0.0f;
+    bool elig = (u - (int)R.last_t) <= P.max_consecutive_misses + 1;
+    if (elig && R.len == 3) elig = is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2);
+    if (elig && nc > 0) {
+        const float dzc = Zc - R.zb;
+        const uint16_t qe = phi16(R.xb + R.tx * dzc, R.yb + R.ty * dzc);
+        const uint16_t lo = (uint16_t)(qe - Wf);
+        int st = win_lower_bound<kLds>(wc, lo);
+        if (st == nc) st = 0;
+        for (int j = 0; j < nc; ++j) {
+            int pc = st + j;
+            if (pc >= nc) pc -= nc;
+            const uint16_t qc = wc.q[pc];
+            if ((uint16_t)(qc - lo) > span) break;
+            const uint16_t id = wc.id[pc];
+            if (!is_free(own, id)) continue;
+            const float dz = wc.z[pc] - R.zb;
+            const float dx = (R.xb + R.tx * dz) - wc.x[pc];
+            const float dy = (R.yb + R.ty * dz) - wc.y[pc];
+            const float sc = (dx * dx) + (dy * dy);
+            if (!(sc < Sf)) continue;
+            if (best == kNone || sc < bsc || (sc == bsc && id < best)) {
+                best = id;
+                bpos = pc;
+                bsc = sc;
+            }
+        }
+        if (best != kNone) {
+            const unsigned long long kap = claim_key(bsc, R.key, u);
+            atomicMin(&claim[best], kap);
+            if (R.len == 3) {
+                atomicMin(&claim[R.h0], kap);
+                atomicMin(&claim[R.h1], kap);
+                atomicMin(&claim[R.h2], kap);
+            }
+        }
+    }
+    bsc_out = bsc;
+    return best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
+}
+
+// search result of active slot a (record r): LDS for the first cap slots
+__device__ __forceinline__ void put_result(const Lds &L, const Work &W, int hb, int cap, int a, int r, uint32_t pb,
+                                           float bsc)
+{
+    if (a < cap) {
+        L.sbest[a] = pb;
+        L.sbsc[a] = bsc;
+    } else {
+        W.rbest[hb + r] = pb;
+        W.rbsc[hb + r] = bsc;
+    }
+}
+
+// Seeding(t), t >= 2 (Section 3), fused with the following search into
+// t+1.  Seeding: modules A = kmod(t-2), Bm = kmod(t-1), C = kmod(t); work
+// items are (unflagged middle hit, partner rank c) -- with K a power of two
+// up to 16, the K doublets of a middle hit run on K adjacent lanes and their
+// best triplets are reduced with lane shuffles, otherwise one lane handles
+// all K.  A new seed's following search into t+1 runs on the lane that made
+// it.  The tracks kept by the last resolution (active slots [0, n_keep))
+// search t+1 on waves of their own.  Both read the flags as the resolution
+// of t left them, which is the state the following of t+1 starts from.
 template <int B, bool kLds>
-__device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
-                              const uint32_t *own, const AList &nxt, int *n_nxt)
+__device__ void stage_seed_follow(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
+                                  const uint32_t *own, const AList &nxt, int *n_nxt, int n_keep, bool follow_next)
 {
     const Win wa = window<B, kLds>(P, L, S, W, hb, t - 2);
     const Win wb = window<B, kLds>(P, L, S, W, hb, t - 1);
     const Win wc = window<B, kLds>(P, L, S, W, hb, t);
+    Win wn = wc;
+    float Zn = 0.0f;
+    if (follow_next) {
+        wn = window<B, kLds>(P, L, S, W, hb, t + 1);
+        Zn = P.module_z[kmod(P, t + 1)];
+    }
+    unsigned long long *__restrict__ claim = W.claim + hb;
     const int na = wa.n, nbm = wb.n;
     const float Zc = P.module_z[kmod(P, t)];
     const float Ss = P.max_scatter_seeding;
@@ -709,13 +789,28 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
     // the lists are in LDS in the LDS instantiation, in memory otherwise
     if (kLds) lds_barrier();
     else __syncthreads();
-    if (nf == 0 || nfm == 0) return;
     const int hd = na >> 1, hu = na - hd - 1;   // offsets visited: [-hd, hu]
     const int G = (K == 1 || K == 2 || K == 4 || K == 8 || K == 16) ? K : 1;
     const int per_lane = G == 1 ? K : 1;
+    const int seed_items = (nf > 0 && nfm > 0) ? nfm * G : 0;
+    const int seed_pad = (seed_items + 63) & ~63;      // seeding and following never share a wave
+    const int follow_items = follow_next ? n_keep : 0;
+    const int total = seed_pad + follow_items;
 
-    for (int base = 0; base < nfm * G; base += B) {
+    for (int base = 0; base < total; base += B) {
         const int g = base + (int)threadIdx.x;
+        const int g_wave = uni(base + ((int)threadIdx.x & ~63));
+        if (g_wave >= seed_pad) {
+            const int a = g - seed_pad;
+            if (a < follow_items) {
+                const int r = nxt.get(a);
+                const Rec R = W.rec[hb + r];
+                float bsc;
+                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, claim, R, t + 1, bsc);
+                put_result(L, W, hb, nxt.cap, a, r, pb, bsc);
+            }
+            continue;
+        }
         const int i = g / G, c = g - i * G;
         SeedBest best;
         best.found = false;
@@ -726,7 +821,7 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
         best.pos2 = 0;
         int p1 = 0;
         float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f;
-        if (i < nfm) {
+        if (g < seed_items) {
             p1 = FM[i];
             x1 = wb.x[p1]; y1 = wb.y[p1]; z1 = wb.z[p1];
             int s0 = win_lower_bound<kLds>(wa, wb.q[p1]);
@@ -749,7 +844,7 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
             o.pos2 = __shfl_xor(best.pos2, m);
             if (seed_better(o, best)) best = o;
         }
-        const bool emit = best.found && c == 0 && i < nfm;
+        const bool emit = best.found && c == 0 && g < seed_items;
         const int r = wave_append(emit, &S.cnt[0]);
         const int l = wave_append(emit, n_nxt);
         if (emit) {
@@ -773,75 +868,11 @@ __device__ void stage_seeding(const sbt_params &P, const Work &W, int hb, int t,
             const float n2 = ((v0 * v0) + (v1 * v1)) + (v2 * v2);
             W.rchi2[hb + r] = ((ssx * ssx) + (ssy * ssy)) / n2;
             nxt.put(l, (uint16_t)r);
-        }
-    }
-}
-
-// ---------------------------------------------------------------- following
-// Search against the flags at stage start, then claim (Section 3, "track
-// following"; conflicting claims resolved by minimum (scatter, key)).
-// rbest packs the best hit's id (low 16 bits) and its window position.
-template <int B, bool kLds>
-__device__ void stage_follow_search(const sbt_params &P, const Work &W, int hb, int t, const Shared<B> &S,
-                                    const Lds &L, const uint32_t *own, const AList &act, int n_act)
-{
-    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
-    const int nc = wc.n;
-    const float Zc = P.module_z[kmod(P, t)];
-    const float Sf = P.max_scatter_forwarding;
-    const uint16_t Wf = (uint16_t)P.phi_window_forwarding;
-    const uint16_t span = (uint16_t)(2 * P.phi_window_forwarding);
-    unsigned long long *__restrict__ claim = W.claim + hb;
-    for (int a = threadIdx.x; a < n_act; a += B) {
-        const int r = act.get(a);
-        const Rec R = W.rec[hb + r];
-        uint16_t best = kNone;
-        int bpos = 0;
-        float bsc = 0.0f;
-        bool elig = (t - (int)R.last_t) <= P.max_consecutive_misses + 1;
-        if (elig && R.len == 3)
-            elig = is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2);
-        if (elig && nc > 0) {
-            const float dzc = Zc - R.zb;
-            const uint16_t qe = phi16(R.xb + R.tx * dzc, R.yb + R.ty * dzc);
-            const uint16_t lo = (uint16_t)(qe - Wf);
-            int st = win_lower_bound<kLds>(wc, lo);
-            if (st == nc) st = 0;
-            for (int j = 0; j < nc; ++j) {
-                int pc = st + j;
-                if (pc >= nc) pc -= nc;
-                const uint16_t qc = wc.q[pc];
-                if ((uint16_t)(qc - lo) > span) break;
-                const uint16_t id = wc.id[pc];
-                if (!is_free(own, id)) continue;
-                const float dz = wc.z[pc] - R.zb;
-                const float dx = (R.xb + R.tx * dz) - wc.x[pc];
-                const float dy = (R.yb + R.ty * dz) - wc.y[pc];
-                const float sc = (dx * dx) + (dy * dy);
-                if (!(sc < Sf)) continue;
-                if (best == kNone || sc < bsc || (sc == bsc && id < best)) {
-                    best = id;
-                    bpos = pc;
-                    bsc = sc;
-                }
+            if (follow_next) {
+                float bsc;
+                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, claim, R, t + 1, bsc);
+                put_result(L, W, hb, nxt.cap, l, r, pb, bsc);
             }
-            if (best != kNone) {
-                const unsigned long long kap = claim_key(bsc, R.key, t);
-                atomicMin(&claim[best], kap);
-                if (R.len == 3) {
-                    atomicMin(&claim[R.h0], kap);
-                    atomicMin(&claim[R.h1], kap);
-                    atomicMin(&claim[R.h2], kap);
-                }
-            }
-        }
-        const uint32_t pb = best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
-        if (a < act.cap) {
-            L.sbest[a] = pb;
-            L.sbsc[a] = bsc;
-        } else {
-            W.rbest[hb + r] = pb;
-            W.rbsc[hb + r] = bsc;
         }
     }
 }
@@ -939,7 +970,7 @@ __device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int 
     }
     RingStage<B> R;
     if (kLds)
-        for (int u = 0; u < 3; ++u) {
+        for (int u = 0; u < 4 && u < M; ++u) {
             ring_load<B>(P, W, hb, u, S, L, R);
             ring_store<B>(P, W, hb, u, S, L, R);
         }
@@ -947,26 +978,23 @@ __device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int 
     const AList l0 = {kLds ? L.al0 : nullptr, W.act0 + hb, kLds ? L.cap : 0};
     const AList l1 = {kLds ? L.al1 : nullptr, W.act1 + hb, kLds ? L.cap : 0};
     int par = 0;
-    if (kLds && M > 3) ring_load<B>(P, W, hb, 3, S, L, R);
-    stage_seeding<B, kLds>(P, W, hb, 2, S, L, own, l0, &S.cnt[1]);
-    if (kLds && M > 3) ring_store<B>(P, W, hb, 3, S, L, R);
+    stage_seed_follow<B, kLds>(P, W, hb, 2, S, L, own, l0, &S.cnt[1], 0, M > 3);
     __syncthreads();
     for (int t = 3; t < M; ++t) {
+        // act (n_act tracks) holds every forming track with its search into
+        // t done: resolve t keeping the survivors in nxt, then seed t and
+        // search t+1
         const int n_act = uni(S.cnt[1 + par]);
         const AList &act = par ? l1 : l0;
         const AList &nxt = par ? l0 : l1;
-        if (threadIdx.x == 0) S.cnt[1 + (par ^ 1)] = 0;
-        stage_follow_search<B, kLds>(P, W, hb, t, S, L, own, act, n_act);
-        __syncthreads();
+        const bool more = t + 1 < M;
+        if (kLds && more) ring_load<B>(P, W, hb, t + 1, S, L, R);
         stage_follow_resolve<B, kLds>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
-        // seeding reads only LDS state written so far (flags, slots, lists);
-        // with the flags in memory the full barrier is needed
-        if (kLds) lds_barrier();
-        else __syncthreads();
-        const bool more = kLds && t + 1 < M;
-        if (more) ring_load<B>(P, W, hb, t + 1, S, L, R);
-        stage_seeding<B, kLds>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)]);
-        if (more) ring_store<B>(P, W, hb, t + 1, S, L, R);
+        if (kLds && more) ring_store<B>(P, W, hb, t + 1, S, L, R);
+        __syncthreads();
+        const int n_keep = uni(S.cnt[1 + (par ^ 1)]);
+        if (threadIdx.x == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
+        stage_seed_follow<B, kLds>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
         __syncthreads();
         par ^= 1;
     }
