@@ -29,6 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+WORKLOADS = {
+    "mu7.6": "{E} events, Poisson(7.6) vertices x Poisson(40) tracks, 26 planes, 99% hit efficiency, 1% noise (seed 2)",
+    "mu1-25": "{E} events, U{{1..25}} vertices x Poisson(40) tracks, 26 planes, 99% hit efficiency, 1% noise (seed 3)",
+    "mu30": "{E} events, Poisson(30) vertices x Poisson(40) tracks, 26 planes, 97% hit efficiency, 5% noise, "
+            "20% of tracks kinked by N(0, 2 mrad) (seed 4)",
+}
 KERNEL = "k_persistent"
 
 
@@ -81,7 +87,7 @@ def serving_leg(params, seconds, fraction=0.5):
     return res
 
 
-def cpu_baseline(batch, gpu_out, target_s=12.0):
+def cpu_baseline(batch, gpu_out, workload="mu7.6", target_s=12.0):
     """The oracle as it stands, single-threaded, on a bounded sample of the
     same events; also confirms the GPU track sets on that sample."""
     import oracle
@@ -102,7 +108,7 @@ def cpu_baseline(batch, gpu_out, target_s=12.0):
     ok = (np.array_equal(eto[:n + 1], want[0]) and np.array_equal(tho[:T + 1], want[1])
           and np.array_equal(th[:int(tho[T])], want[2]))
     return dict(value=round(n / dt, 2), unit="events/s", cores=1, kind="oracle",
-                sample=f"first {n} events of the mu=7.6 batch, one pass, single thread",
+                sample=f"first {n} events of the {workload} batch, one pass, single thread",
                 hits_per_s=round(int(sub.n_hits) / dt, 1), gpu_matches_oracle_on_sample=bool(ok))
 
 
@@ -111,7 +117,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--events", type=int, default=1000)
+    ap.add_argument("--workload", default="mu7.6", choices=["mu7.6", "mu1-25", "mu30"],
+                    help="mu7.6: 1,000 events (the headline); mu1-25: 10,000 uneven events; mu30: 2,000 dense events")
+    ap.add_argument("--events", type=int, default=0, help="events (0: the workload's size)")
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -131,7 +139,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    batch = synth.make_batch("mu7.6", args.events)
+    batch = synth.make_batch(args.workload, args.events or None)
     E, H = batch.n_events, batch.n_hits
     params = sbt.make_params(batch.module_z)
     dev = sbt.DeviceBatch(batch)
@@ -142,7 +150,7 @@ def main():
         ctx.set_tuning(sbt.make_tuning(args.tpe, args.bpc, args.cap))
         tuned_ms = None
     else:
-        best, tuned_ms = ctx.autotune(dev, reps=3)
+        best, tuned_ms = ctx.autotune(dev, reps=3, cache=False)
     tuning = ctx.get_tuning().as_dict()
     stream = torch.cuda.current_stream()
 
@@ -192,8 +200,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{E} events, Poisson(7.6) vertices x Poisson(40) tracks, 26 planes, "
-                               "99% hit efficiency, 1% noise (seed 2)",
+        "config": {"workload": WORKLOADS[args.workload].format(E=E),
                    "n_events": E, "n_hits": H, "tuning": tuning},
         "hits_per_s": round(H / sec_batched, 1),
         "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
@@ -213,7 +220,7 @@ def main():
         result["serving"] = serving_leg(params, args.serve_seconds)
         result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
     if not args.no_cpu:
-        result["cpu_baseline"] = cpu_baseline(batch, got)
+        result["cpu_baseline"] = cpu_baseline(batch, got, args.workload)
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

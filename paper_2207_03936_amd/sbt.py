@@ -329,14 +329,82 @@ class Context:
                                              _stream_handle(stream)), "sbt_reconstruct_batched")
         return out
 
-    def autotune(self, sample: DeviceBatch, reps: int = 3, stream=None):
+    def autotune(self, sample: DeviceBatch, reps: int = 3, stream=None, cache: bool = True):
+        """Time the launch configurations on `sample` and install the fastest.
+        With cache, a result stored for the same GPU architecture and batch
+        shape (events, mean and largest event size, in coarse buckets) is
+        installed without timing; new results are stored.  Returns
+        (SbtTuning, ms per launch or None when taken from the cache)."""
+        key = _tune_key(sample) if cache else None
+        if key is not None:
+            hit = _tune_cache_get(key)
+            if hit is not None:
+                t = make_tuning(**hit)
+                self.set_tuning(t)
+                return t, None
         out = DeviceTracks(sample.n_events, sample.n_hits)
         best = SbtTuning()
         ms = ctypes.c_float(0)
         _check(lib().sbt_autotune(self.handle, ctypes.byref(sample.hits), ctypes.byref(out.tracks),
                                   _stream_handle(stream), int(reps), ctypes.byref(best), ctypes.byref(ms)),
                "sbt_autotune")
+        if key is not None:
+            _tune_cache_put(key, best.as_dict())
         return best, float(ms.value)
+
+
+# ------------------------------------------------------------------ autotune cache
+# JSON file: {"<arch>|E<bucket>|N<bucket>|X<bucket>": tuning dict}.  The
+# location is $SBT_TUNE_CACHE, else ~/.cache/sbt/tuning.json.
+
+def _tune_cache_path() -> str:
+    return os.environ.get("SBT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "sbt", "tuning.json"))
+
+
+def _bucket(v: float) -> int:
+    """Coarse bucket: nearest power of sqrt(2), rounded to an integer."""
+    import math
+    v = max(1.0, float(v))
+    return int(round(2.0 ** (round(2.0 * math.log2(v)) / 2.0)))
+
+
+def _tune_key(sample: "DeviceBatch"):
+    torch = _torch()
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    eo = sample.eo.cpu().numpy()[:sample.n_events + 1]
+    mo = sample.mo.cpu().numpy()[:sample.n_events * sample.n_modules + 1]
+    sizes = np.diff(eo)
+    mean = float(sizes.mean()) if sizes.size else 0.0
+    big = int(np.diff(mo).max()) if mo.size > 1 else 0
+    return f"{arch}|E{_bucket(sample.n_events)}|N{_bucket(mean)}|X{_bucket(big)}"
+
+
+def _tune_cache_get(key):
+    import json
+    try:
+        with open(_tune_cache_path()) as f:
+            return json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+
+
+def _tune_cache_put(key, value):
+    import json
+    path = _tune_cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        try:
+            with open(path) as f:
+                data = json.load(f)
+        except (OSError, ValueError):
+            data = {}
+        data[key] = value
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
 
 
 def sbt_context_create(params, max_events, max_hits, tuning=None) -> Context:

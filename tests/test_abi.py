@@ -90,3 +90,13 @@ def test_product_path_fails_loudly_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         sbt.DeviceBatch(synth.make_batch("tiny", 1))
+
+
+def test_tune_cache_roundtrip(tmp_path, monkeypatch):
+    monkeypatch.setenv("SBT_TUNE_CACHE", str(tmp_path / "t.json"))
+    assert sbt._tune_cache_get("gfx950|E1|N1|X1") is None
+    sbt._tune_cache_put("gfx950|E1|N1|X1", dict(threads_per_event=512, blocks_per_cu=2, lds_window_hits=672,
+                                                 lds_owner_hits=16384))
+    got = sbt._tune_cache_get("gfx950|E1|N1|X1")
+    assert got["threads_per_event"] == 512 and got["lds_window_hits"] == 672
+    assert [sbt._bucket(v) for v in (1, 2, 3, 4, 5, 6, 8, 1000)] == [1, 2, 3, 4, 6, 6, 8, 1024]
