@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (0: autotune)")
     ap.add_argument("--cap", type=int, default=672, help="LDS slot capacity in hits (with --tpe/--bpc)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="also run a device-to-device copy of this many MiB (counter calibration)")
+                    help="also run one elementwise multiply over this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so "
