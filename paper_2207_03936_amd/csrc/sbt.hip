@@ -1,11 +1,11 @@
 // Search by triplet for MI355X (gfx950): kernels and the C ABI of include/sbt.h.
 //
 // Plain form: one workgroup per event and one launch per stage.
-// Batched form: a persistent work-stealing kernel that runs every stage of an
-// event inside one workgroup and then takes the next event from a device
-// counter, followed by a scan over events and the CSR write, replayed as one
-// captured HIP graph.  Both forms share the device stages of sbt_device.h and
-// give byte-identical outputs.
+// Batched form: a persistent work-stealing kernel (sbt_persistent.hip) that
+// runs every stage of an event inside one workgroup and then takes the next
+// event from a device counter, followed by a scan over events and the CSR
+// write, replayed as one captured HIP graph.  Both forms share the device
+// stages of sbt_device.h and give byte-identical outputs.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -18,6 +18,7 @@
 #include "sbt.h"
 #include "sbt_device.h"
 #include "sbt_internal.h"
+#include "sbt_kernels.h"
 
 using namespace sbt;
 
@@ -25,54 +26,55 @@ using namespace sbt;
 
 // plain form ----------------------------------------------------------------
 
+constexpr int kPlainThreads = 256;
+constexpr int kPlainCap = 672;
+constexpr int kPlainOwnCap = 16384;
+
 template <int B>
-__global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
+__global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W, int sortcap)
 {
     __shared__ Shared<B> S;
-    extern __shared__ char dyn[];
-    const Lds L = carve_lds(dyn, cap, own_cap);
     const int e = blockIdx.x;
     int hb, N;
     const int st = load_event<B>(P, H, e, S, &hb, &N);
-    if (threadIdx.x == 0) W.ev_st[e] = st;
+    if (threadIdx.x == 0) ws_evinfo(W)[e].st = st;
     if (st != 0) return;
-    stage_sort<B>(P, H, W, hb, N, S, L);
+    stage_sort<B>(P, H, event_view(W, e, hb, N), S, sortcap);
 }
 
-template <int B>
-__global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
+template <int B, int CAP>
+__global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W, int own_cap)
 {
     __shared__ Shared<B> S;
-    extern __shared__ char dyn[];
-    const Lds L = carve_lds(dyn, cap, own_cap);
     const int e = blockIdx.x;
-    if (W.ev_st[e] != 0) return;
+    if (ws_evinfo(W)[e].st != 0) return;
     int hb, N;
     load_event<B>(P, H, e, S, &hb, &N);
-    stage_track<B>(P, W, e, hb, N, S, L, true);
-    if (threadIdx.x == 0) W.ev_nfin[e] = S.cnt[3];
+    stage_track<B, CAP>(P, event_view(W, e, hb, N), S, own_cap, true);
+    if (threadIdx.x == 0) ws_evinfo(W)[e].nfin = S.cnt[3];
 }
 
 template <int B>
 __global__ __launch_bounds__(B) void k_weak_filter(sbt_params P, HitsArgs H, Work W)
 {
     const int e = blockIdx.x;
-    if (W.ev_st[e] != 0) return;
+    if (ws_evinfo(W)[e].st != 0) return;
     const int hb = H.eo[e];
-    stage_filter<B>(P, W, hb, W.ev_nfin[e], owner_words(W, e, hb));
+    const Ev v = event_view(W, e, hb, H.eo[e + 1] - hb);
+    stage_filter<B>(P, v, ws_evinfo(W)[e].nfin, v.own());
 }
 
 template <int B>
 __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
 {
-    __shared__ int scan[B / 64 + 1];
+    __shared__ int scan[2 * (B / 64)];
     const int e = blockIdx.x;
-    if (W.ev_st[e] != 0) {
-        if (threadIdx.x == 0) { W.ev_nt[e] = 0; W.ev_nh[e] = 0; }
+    if (ws_evinfo(W)[e].st != 0) {
+        if (threadIdx.x == 0) { ws_evinfo(W)[e].nt = 0; ws_evinfo(W)[e].nh = 0; }
         return;
     }
     const int hb = H.eo[e];
-    stage_compact<B>(W, e, hb, H.eo[e + 1] - hb, scan);
+    stage_compact<B>(event_view(W, e, hb, H.eo[e + 1] - hb), scan);
 }
 
 // batched form ----------------------------------------------------------------
@@ -86,8 +88,8 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 {
     __shared__ int hist[kOrderClasses + 1];
     __shared__ int fill[kOrderClasses];
-    __shared__ int sw[kOrderThreads / 64 + 1];
-    if (threadIdx.x == 0) *W.counter = 0u;
+    __shared__ int sw[2 * (kOrderThreads / 64)];
+    if (threadIdx.x == 0) *ws_counterp(W) = 0u;
     for (int i = threadIdx.x; i <= kOrderClasses; i += kOrderThreads) hist[i] = 0;
     for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) fill[i] = 0;
     __syncthreads();
@@ -106,37 +108,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
         int cls = n < 0 ? 0 : (n >> 6);
         cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
         const int k = kOrderClasses - 1 - cls;
-        W.order[hist[k] + atomicAdd(&fill[k], 1)] = e;
-    }
-}
-
-template <int B>
-__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W, int cap, int own_cap)
-{
-    __shared__ Shared<B> S;
-    extern __shared__ char dyn[];
-    const Lds L = carve_lds(dyn, cap, own_cap);
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const int idx = (int)atomicAdd(W.counter, 1u);
-            S.e = idx < H.n_events ? W.order[idx] : -1;
-        }
-        __syncthreads();
-        const int e = uni(S.e);
-        if (e < 0) break;
-        int hb, N;
-        const int st = load_event<B>(P, H, e, S, &hb, &N);
-        if (threadIdx.x == 0) W.ev_st[e] = st;
-        if (st == 0) {
-            stage_sort<B>(P, H, W, hb, N, S, L);
-            stage_track<B>(P, W, e, hb, N, S, L, false);
-            stage_filter<B>(P, W, hb, uni(S.cnt[3]), owner_ptr<B>(S, L, W, e, hb, N));
-            stage_compact<B>(W, e, hb, N, S.scan);
-        } else if (threadIdx.x == 0) {
-            W.ev_nt[e] = 0;
-            W.ev_nh[e] = 0;
-        }
-        __syncthreads();
+        ws_orderp(W)[hist[k] + atomicAdd(&fill[k], 1)] = e;
     }
 }
 
@@ -147,23 +119,23 @@ constexpr int kScanThreads = 1024;
 __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutArgs O)
 {
     const int E = H.n_events;
-    __shared__ int sw[kScanThreads / 64 + 1];
+    __shared__ int sw[2 * (kScanThreads / 64)];
     const int chunk = (E + kScanThreads - 1) / kScanThreads;
     const int beg = threadIdx.x * chunk;
     const int end = min(beg + chunk, E);
     int st = 0, sh = 0;
     for (int i = beg; i < end; ++i) {
-        st += W.ev_nt[i];
-        sh += W.ev_nh[i];
+        st += ws_evinfo(W)[i].nt;
+        sh += ws_evinfo(W)[i].nh;
     }
     int tt, th;
-    int ot = block_excl_scan<kScanThreads>(st, sw, &tt);
-    int oh = block_excl_scan<kScanThreads>(sh, sw, &th);
+    int ot = block_excl_scan<kScanThreads>(st, sw, 0, &tt);
+    int oh = block_excl_scan<kScanThreads>(sh, sw, 1, &th);
     for (int i = beg; i < end; ++i) {
         O.eto[i] = ot;
-        W.ev_hb[i] = oh;
-        ot += W.ev_nt[i];
-        oh += W.ev_nh[i];
+        ws_evinfo(W)[i].out_h = oh;
+        ot += ws_evinfo(W)[i].nt;
+        oh += ws_evinfo(W)[i].nh;
     }
     if (threadIdx.x == 0) {
         O.eto[E] = tt;
@@ -175,13 +147,13 @@ constexpr int kWriteThreads = 256;
 __global__ __launch_bounds__(kWriteThreads) void k_write(HitsArgs H, Work W, OutArgs O)
 {
     for (int e = blockIdx.x; e < H.n_events; e += gridDim.x) {
-        if (O.status && threadIdx.x == 0) O.status[e] = W.ev_st[e];
-        const int nt = W.ev_nt[e], nh = W.ev_nh[e];
+        if (O.status && threadIdx.x == 0) O.status[e] = ws_evinfo(W)[e].st;
+        const int nt = ws_evinfo(W)[e].nt, nh = ws_evinfo(W)[e].nh;
         if (nt == 0) continue;
         const int hb = H.eo[e];
-        const int t0 = O.eto[e], p0 = W.ev_hb[e];
-        for (int i = threadIdx.x; i < nt; i += kWriteThreads) O.tho[t0 + i] = p0 + W.st_toff[hb + i];
-        for (int j = threadIdx.x; j < nh; j += kWriteThreads) O.th[p0 + j] = W.st_hits[hb + j];
+        const int t0 = O.eto[e], p0 = ws_evinfo(W)[e].out_h;
+        for (int i = threadIdx.x; i < nt; i += kWriteThreads) O.tho[t0 + i] = p0 + ws_toff(W)[hb + i];
+        for (int j = threadIdx.x; j < nh; j += kWriteThreads) O.th[p0 + j] = ws_sthits(W)[hb + j];
     }
 }
 
@@ -189,8 +161,9 @@ __global__ __launch_bounds__(kWriteThreads) void k_write(HitsArgs H, Work W, Out
 __global__ void k_copy_sorted(int H, Work W, uint16_t *phi, uint16_t *ids)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < H; i += gridDim.x * blockDim.x) {
-        phi[i] = W.sq[i];
-        ids[i] = W.sid[i];
+        const uint32_t qid = ws_hs(W)[i].qid;
+        phi[i] = (uint16_t)(qid & 0xFFFFu);
+        ids[i] = (uint16_t)(qid >> 16);
     }
 }
 
@@ -200,50 +173,17 @@ namespace {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-// Carves the workspace; with base == nullptr only the size is computed.
+// Lays out the workspace; with base == nullptr only the size is computed.
 size_t carve(int32_t E, int32_t H, char *base, Work *W)
 {
-    size_t off = 0;
-    auto take = [&](size_t bytes) -> char * {
-        char *p = base ? base + off : nullptr;
-        off += align_up(bytes ? bytes : 1);
-        return p;
-    };
-    const size_t h = (size_t)(H > 0 ? H : 1);
-    const size_t e = (size_t)(E > 0 ? E : 1);
-    Work w;
-    w.keys = (uint32_t *)take(4 * h);
-    w.sx = (float *)take(4 * h);
-    w.sy = (float *)take(4 * h);
-    w.sz = (float *)take(4 * h);
-    w.sq = (uint16_t *)take(2 * h);
-    w.sid = (uint16_t *)take(2 * h);
-    w.owner = (uint32_t *)take(4 * (h / 32 + e + 2));
-    w.claim = (unsigned long long *)take(8 * h);
-    w.prev = (uint16_t *)take(2 * h);
-    w.rec = (Rec *)take(sizeof(Rec) * h);
-    w.rbest = (uint32_t *)take(4 * h);
-    w.rbsc = (float *)take(4 * h);
-    w.rchi2 = (float *)take(4 * h);
-    w.rflag = (uint8_t *)take(h);
-    w.act0 = (uint16_t *)take(2 * h);
-    w.act1 = (uint16_t *)take(2 * h);
-    w.fin = (uint16_t *)take(2 * h);
-    w.freel = (uint16_t *)take(2 * h);
-    w.freem = (uint16_t *)take(2 * h);
-    w.frank = (uint16_t *)take(2 * h);
-    w.key2rec = (uint16_t *)take(2 * h);
-    w.st_hits = (uint16_t *)take(2 * h);
-    w.st_toff = (int32_t *)take(4 * h);
-    w.ev_nt = (int32_t *)take(4 * e);
-    w.ev_nh = (int32_t *)take(4 * e);
-    w.ev_hb = (int32_t *)take(4 * e);
-    w.ev_st = (int32_t *)take(4 * e);
-    w.ev_nfin = (int32_t *)take(4 * e);
-    w.order = (int32_t *)take(4 * e);
-    w.counter = (unsigned int *)take(256);
-    if (W) *W = w;
-    return off;
+    const uint32_t h = (uint32_t)(((size_t)(H > 0 ? H : 1) + 255) / 256 * 256);
+    const uint32_t e = (uint32_t)(E > 0 ? E : 1);
+    if (W) {
+        W->base = base;
+        W->H = h;
+        W->E = e;
+    }
+    return (size_t)ws_bytes(h, e);
 }
 
 bool is_pow_tpe(int v) { return v == 64 || v == 128 || v == 256 || v == 512; }
@@ -294,18 +234,12 @@ OutArgs out_args(const sbt_tracks *t)
         if ((expr) != hipSuccess) return SBT_ERR_HIP;   \
     } while (0)
 
-constexpr int kPlainThreads = 256;
-
-constexpr int kPlainCap = 672;
-constexpr int kPlainOwnCap = 16384;
-
 int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hipStream_t s)
 {
     const dim3 g(H.n_events), b(kPlainThreads);
-    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, lds_bytes(kPlainCap, kPlainOwnCap), s, P, H, W, kPlainCap,
-                       kPlainOwnCap);
-    hipLaunchKernelGGL(k_seed_follow<kPlainThreads>, g, b, lds_bytes(kPlainCap, kPlainOwnCap), s, P, H, W,
-                       kPlainCap, kPlainOwnCap);
+    const uint32_t lds = lds_bytes(kPlainCap, kPlainOwnCap);
+    hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, lds, s, P, H, W, lds_sortcap(kPlainCap, kPlainOwnCap));
+    hipLaunchKernelGGL((k_seed_follow<kPlainThreads, kPlainCap>), g, b, lds, s, P, H, W, kPlainOwnCap);
     hipLaunchKernelGGL(k_weak_filter<kPlainThreads>, g, b, 0, s, P, H, W);
     hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, 0, s, H, W);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
@@ -319,15 +253,24 @@ int launch_tail(const HitsArgs &H, const Work &W, const OutArgs &O, hipStream_t 
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
 }
 
-typedef void (*persistent_fn)(sbt_params, HitsArgs, Work, int, int);
+// the compiled slot capacity a requested one runs with: the largest not above it
+int effective_cap(int requested)
+{
+    int c = 0;
+    for (int i = 0; i < kNumCaps; ++i)
+        if (kCaps[i] <= requested) c = kCaps[i];
+    return c;
+}
 
-persistent_fn persistent_kernel(int tpe)
+uint32_t tuning_lds(const sbt_tuning &T) { return lds_bytes(effective_cap(T.lds_window_hits), T.lds_owner_hits); }
+
+const void *persistent_kernel(int tpe, int cap)
 {
     switch (tpe) {
-    case 64: return k_persistent<64>;
-    case 128: return k_persistent<128>;
-    case 256: return k_persistent<256>;
-    case 512: return k_persistent<512>;
+    case 64: return persistent_kernel_64(cap);
+    case 128: return persistent_kernel_128(cap);
+    case 256: return persistent_kernel_256(cap);
+    case 512: return persistent_kernel_512(cap);
     default: return nullptr;
     }
 }
@@ -340,26 +283,31 @@ int device_cus(int *cus)
     return SBT_OK;
 }
 
-// Allows dynamic LDS above 64 KiB for the persistent kernel of this width.
-int allow_lds(int tpe, size_t bytes)
+// Allows dynamic LDS above 64 KiB for a persistent kernel.
+int allow_lds(const void *fn, size_t bytes)
 {
     if (bytes <= 64 * 1024) return SBT_OK;
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(persistent_kernel(tpe)),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    return SBT_OK;
+}
+
+// resident workgroups per CU of the persistent kernel under a tuning
+int persistent_occupancy(const sbt_tuning &T, int *occ)
+{
+    const void *fn = persistent_kernel(T.threads_per_event, effective_cap(T.lds_window_hits));
+    if (!fn) return SBT_ERR_INVALID_ARG;
+    const size_t lds = tuning_lds(T);
+    if (int rc = allow_lds(fn, lds)) return rc;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, fn, T.threads_per_event, lds));
     return SBT_OK;
 }
 
 int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
 {
-    const size_t lds = lds_bytes(T.lds_window_hits, T.lds_owner_hits);
-    if (int rc = allow_lds(T.threads_per_event, lds)) return rc;
-    int cus = 0;
+    int cus = 0, occ = 0;
     int rc = device_cus(&cus);
     if (rc) return rc;
-    int occ = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, reinterpret_cast<const void *>(persistent_kernel(T.threads_per_event)), T.threads_per_event,
-        lds_bytes(T.lds_window_hits, T.lds_owner_hits)));
+    if ((rc = persistent_occupancy(T, &occ))) return rc;
     int bpc = std::max(1, std::min(T.blocks_per_cu, std::max(occ, 1)));
     *grid = std::max(1, std::min(cus * bpc, std::max(n_events, 1)));
     return SBT_OK;
@@ -371,11 +319,18 @@ int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, 
     int grid = 0;
     int rc = persistent_grid(T, H.n_events, &grid);
     if (rc) return rc;
+    const int cap = effective_cap(T.lds_window_hits);
+    const uint32_t lds = tuning_lds(T);
+    int own_cap = T.lds_owner_hits;
+    int sortcap = lds_sortcap(cap, T.lds_owner_hits);
+    sbt_params Pc = P;
+    HitsArgs Hc = H;
+    Work Wc = W;
+    void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap};
     if (marks) HIP_TRY(hipEventRecord(marks[0], s));
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
-    hipLaunchKernelGGL(persistent_kernel(T.threads_per_event), dim3(grid), dim3(T.threads_per_event),
-                       lds_bytes(T.lds_window_hits, T.lds_owner_hits), s, P, H, W, T.lds_window_hits,
-                       T.lds_owner_hits);
+    HIP_TRY(hipLaunchKernel(persistent_kernel(T.threads_per_event, cap), dim3(grid), dim3(T.threads_per_event), args,
+                            lds, s));
     if (marks) HIP_TRY(hipEventRecord(marks[1], s));
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, H, W, O);
     if (marks) HIP_TRY(hipEventRecord(marks[2], s));
@@ -494,7 +449,7 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
     carve(hits->n_events, hits->n_hits, (char *)workspace, &W);
     const HitsArgs H = hits_args(hits);
     hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, dim3(H.n_events), dim3(kPlainThreads),
-                       lds_bytes(kPlainCap, kPlainOwnCap), s, *params, H, W, kPlainCap, kPlainOwnCap);
+                       lds_bytes(kPlainCap, kPlainOwnCap), s, *params, H, W, lds_sortcap(kPlainCap, kPlainOwnCap));
     hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
                        phi_sorted, ids_sorted);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
@@ -541,7 +496,7 @@ int valid_tuning(const sbt_tuning &t)
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return SBT_ERR_INVALID_ARG;
     if (t.lds_window_hits < 0 || t.lds_window_hits > 2048) return SBT_ERR_INVALID_ARG;
     if (t.lds_owner_hits < 0 || t.lds_owner_hits > 65536) return SBT_ERR_INVALID_ARG;
-    if (lds_bytes(t.lds_window_hits, t.lds_owner_hits) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
+    if (tuning_lds(t) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
     return SBT_OK;
 }
 
@@ -711,7 +666,7 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
     // candidates: lanes per event x LDS slot capacity, each at the largest
     // number of resident workgroups per CU and one less
     const int tpes[] = {128, 256, 512};
-    const int caps[] = {448, 672, 1024, 1536};
+    const int caps[] = {256, 448, 672, 1024, 1536};
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;
     rc = SBT_OK;
@@ -722,14 +677,8 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
             t.lds_window_hits = cap;
             t.lds_owner_hits = 16384;
             if (valid_tuning(t) != SBT_OK) continue;
-            const size_t lds = lds_bytes(cap, t.lds_owner_hits);
-            if ((rc = allow_lds(tpe, lds))) break;
             int occ = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &occ, reinterpret_cast<const void *>(persistent_kernel(tpe)), tpe, lds) != hipSuccess) {
-                rc = SBT_ERR_HIP;
-                break;
-            }
+            if ((rc = persistent_occupancy(t, &occ))) break;
             if (occ < 1) continue;
             for (int bpc = occ; bpc >= 1 && bpc >= occ - 1; --bpc) {
                 t.blocks_per_cu = bpc;

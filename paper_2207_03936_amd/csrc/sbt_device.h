@@ -7,14 +7,19 @@
 //
 // Per-event state lives in the workspace, in regions indexed by the event's
 // absolute hit offset hb (capacity N = hits of the event):
-//   sorted hits   sx, sy, sz, sq (phi16), sid (event-local id)   by sorted position
-//   owner         one bit per hit id: set once a track has taken the hit (the
-//                 method only ever asks whether a hit is flagged; which track
-//                 holds it is settled by the claim keys)
-//   claim         u64 per hit id: minimum claim key of the current stage
-//   prev          u16 per hit id: previous hit of the owning track
-//   rec           32-byte forming-track records (one per seed; <= N)
+//   hs      16-byte sorted hits {x, y, z, phi16 | id << 16} by sorted position
+//   owner   one bit per hit id: set once a track has taken the hit (the
+//           method only ever asks whether a hit is flagged; which track
+//           holds it is settled by the claim keys)
+//   claim   u64 per hit id: minimum claim key of the current stage
+//   link    two u16 per hit id: the previous hit of the owning track, and
+//           the record of the accepted track whose key is this id
+//   rec     32-byte forming-track records (one per seed; <= N) and a 16-byte
+//           auxiliary record each (search result, seed fit, filter outcome)
+//   lists   six u16 lists of the memory instantiation (active tracks x2,
+//           final tracks, unflagged positions x2, unflagged ranks)
 // Hit ids, keys and record indices are 16-bit (events hold <= 65,535 hits).
+// Per-event bases are uniform; per-lane offsets are 32-bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,33 +44,71 @@ struct Rec {
 };
 static_assert(sizeof(Rec) == 32, "record layout");
 
-// record flags
-constexpr uint8_t kFlagCandidate = 2;  // tracklet candidate
-constexpr uint8_t kFlagAccepted = 4;
-
-struct Work {
-    uint32_t *keys;     // sort keys (phi16 << 16 | id) of events too large for LDS
-    float *sx, *sy, *sz;
-    uint16_t *sq, *sid;
-    uint32_t *owner;    // flag bitmaps; event e's starts at word (hb >> 5) + e
-    unsigned long long *claim;
-    uint16_t *prev;
-    Rec *rec;
-    uint32_t *rbest;    // best hit id | window position << 16, or ~0
-    float *rbsc;
-    float *rchi2;
-    uint8_t *rflag;
-    uint16_t *act0, *act1, *fin;
-    uint16_t *freel;    // unflagged-position lists of modules too large for LDS
-    uint16_t *freem;
-    uint16_t *frank;
-    uint16_t *key2rec;
-    uint16_t *st_hits;  // per-event compacted hit ids
-    int32_t *st_toff;   // per-event track hit offsets
-    int32_t *ev_nt, *ev_nh, *ev_hb, *ev_st, *ev_nfin;
-    int32_t *order;     // events, largest first (batched form)
-    unsigned int *counter;
+// per-record auxiliary data
+struct RecAux {
+    uint32_t best;      // memory instantiation: search result (best id | position << 16, or ~0)
+    float bsc;          // its scatter
+    float chi2;         // tracklet fit of the seed
+    uint32_t flag;      // filter outcome
 };
+static_assert(sizeof(RecAux) == 16, "auxiliary record layout");
+
+// sorted hit: coordinates and phi16 | id << 16
+struct alignas(16) Hit16 {
+    float x, y, z;
+    uint32_t qid;
+};
+
+// per-event counters
+struct EvInfo {
+    int32_t nt, nh;     // accepted tracks and their hits
+    int32_t out_h;      // first output hit position (batch scan)
+    int32_t st;         // SBT_EV_* status
+    int32_t nfin;       // final records (plain form)
+    int32_t pad[3];
+};
+
+// record flags
+constexpr uint32_t kFlagCandidate = 2;  // tracklet candidate
+constexpr uint32_t kFlagAccepted = 4;
+
+// memory lists (stride = workspace hit capacity)
+constexpr int kListAct0 = 0, kListAct1 = 1, kListFin = 2, kListFreeL = 3, kListFreeM = 4, kListFRank = 5;
+constexpr int kLists = 6;
+
+// Workspace: one base pointer; every array sits at a fixed multiple of the
+// hit capacity H (a multiple of 256) or, after the per-hit arrays, of the
+// event capacity E.  Per hit: rec 32 B, hs 16, aux 16, claim 8, keys 4 (sort
+// keys of events too large for the LDS sort), link 4, st_toff 4 (per-event
+// track hit offsets), six u16 lists 12, st_hits 2 (per-event compacted hit
+// ids).  Then the flag bitmaps (event e's starts at word (hb >> 5) + e), the
+// per-event counters, the event order (largest first) and the work counter.
+struct Work {
+    char *base;
+    uint32_t H, E;
+};
+
+constexpr uint32_t kOffRec = 0, kOffHs = 32, kOffAux = 48, kOffClaim = 64, kOffKeys = 72, kOffLink = 76,
+                   kOffToff = 80, kOffLists = 84, kOffStHits = 96, kHitBytes = 98;
+
+__host__ __device__ inline uint64_t ws_owner(uint32_t H) { return (uint64_t)H * kHitBytes; }
+__host__ __device__ inline uint64_t ws_ev(uint32_t H, uint32_t E) { return ws_owner(H) + (((uint64_t)H / 32 + E + 2) * 4 + 255) / 256 * 256; }
+__host__ __device__ inline uint64_t ws_order(uint32_t H, uint32_t E) { return ws_ev(H, E) + (uint64_t)E * 32; }
+__host__ __device__ inline uint64_t ws_counter(uint32_t H, uint32_t E) { return ws_order(H, E) + (uint64_t)E * 4; }
+__host__ __device__ inline uint64_t ws_bytes(uint32_t H, uint32_t E) { return ws_counter(H, E) + 256; }
+
+__host__ __device__ inline EvInfo *ws_evinfo(const Work &W) { return (EvInfo *)(W.base + ws_ev(W.H, W.E)); }
+__host__ __device__ inline int32_t *ws_orderp(const Work &W) { return (int32_t *)(W.base + ws_order(W.H, W.E)); }
+__host__ __device__ inline unsigned int *ws_counterp(const Work &W)
+{
+    return (unsigned int *)(W.base + ws_counter(W.H, W.E));
+}
+__host__ __device__ inline Hit16 *ws_hs(const Work &W) { return (Hit16 *)(W.base + (uint64_t)W.H * kOffHs); }
+__host__ __device__ inline int32_t *ws_toff(const Work &W) { return (int32_t *)(W.base + (uint64_t)W.H * kOffToff); }
+__host__ __device__ inline uint16_t *ws_sthits(const Work &W)
+{
+    return (uint16_t *)(W.base + (uint64_t)W.H * kOffStHits);
+}
 
 struct HitsArgs {
     int32_t n_events;
@@ -81,6 +124,18 @@ struct OutArgs {
     int32_t *th;
     int32_t *status;
 };
+
+// element i of an array with a uniform base, addressed with a 32-bit offset
+template <class T>
+__device__ __forceinline__ T &at(T *p, uint32_t i)
+{
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ const T &at(const T *p, uint32_t i)
+{
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) + i * (uint32_t)sizeof(T));
+}
 
 // ---------------------------------------------------------------- phi16
 // Simplified atan2 on 16 bits (Section 3, "Sort by phi"): atan(r), r in
@@ -132,6 +187,40 @@ __device__ __forceinline__ void lds_barrier()
 // moved to a scalar register.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// The value, hidden from the optimiser at this point.  Stages re-read the
+// scalar parameters and the workspace base through this at the start of
+// every module step, so values derived from them are recomputed per step
+// instead of being hoisted out of the event and step loops, where dozens of
+// them would stay live in scalar registers (and spill) for the whole kernel.
+template <class T>
+__device__ __forceinline__ T opq(T v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// scalar parameters of the stages
+struct Prm {
+    int M, rev, K, Ws, Wf, misses;
+    float Ss, Sf, X;
+};
+
+__device__ __forceinline__ Prm fresh(const sbt_params &P)
+{
+    Prm p;
+    p.M = opq(P.n_modules);
+    p.rev = opq(P.reverse);
+    p.K = opq(P.max_doublet_candidates);
+    p.Ws = opq(P.phi_window_seeding);
+    p.Wf = opq(P.phi_window_forwarding);
+    p.misses = opq(P.max_consecutive_misses);
+    p.Ss = __int_as_float(opq(__float_as_int(P.max_scatter_seeding)));
+    p.Sf = __int_as_float(opq(__float_as_int(P.max_scatter_forwarding)));
+    p.X = __int_as_float(opq(__float_as_int(P.max_tracklet_chi2)));
+    return p;
+}
+
+__device__ __forceinline__ int kmod(const Prm &p, int t) { return p.rev ? p.M - 1 - t : t; }
 __device__ __forceinline__ int kmod(const sbt_params &P, int t)
 {
     return P.reverse ? P.n_modules - 1 - t : t;
@@ -151,22 +240,12 @@ __device__ __forceinline__ int module_of(const int *mo, int M, int i)
 // hit flags: one bit per event-local hit id
 __device__ __forceinline__ bool is_free(const uint32_t *own, unsigned id)
 {
-    return ((own[id >> 5] >> (id & 31u)) & 1u) == 0u;
+    return ((at(own, id >> 5) >> (id & 31u)) & 1u) == 0u;
 }
 
 __device__ __forceinline__ void set_flag(uint32_t *own, unsigned id)
 {
-    atomicOr(&own[id >> 5], 1u << (id & 31u));
-}
-
-__device__ __forceinline__ int lower_bound16(const uint16_t *a, int n, uint16_t v)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (a[mid] < v) lo = mid + 1; else hi = mid;
-    }
-    return lo;
+    atomicOr(&at(own, id >> 5), 1u << (id & 31u));
 }
 
 // Claim key of a stage: (255 - stage) in bits 48..55, the score's binary32
@@ -180,54 +259,83 @@ __device__ __forceinline__ unsigned long long claim_key(float score, uint16_t ke
 }
 constexpr int kFilterStage = 64;
 
+// number of set bits of m below this lane
+__device__ __forceinline__ int lane_rank(unsigned long long m)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Append under a predicate with one LDS atomic per wave; every lane of the
 // wave must call it.  Returns the slot, or -1 where pred is false.
 __device__ __forceinline__ int wave_append(bool pred, int *counter)
 {
-    unsigned long long m = __ballot(pred);
+    const unsigned long long m = __ballot(pred);
     if (m == 0) return -1;
-    int lane = __lane_id();
-    int leader = __ffsll((long long)m) - 1;
     int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(m));
-    base = __shfl(base, leader);
-    int rank = __popcll(m & ((1ull << lane) - 1ull));
-    return pred ? base + rank : -1;
+    if (lane_rank(__builtin_amdgcn_read_exec()) == 0) base = atomicAdd(counter, __popcll(m));
+    base = __builtin_amdgcn_readfirstlane(base);
+    return pred ? base + lane_rank(m) : -1;
 }
 
-__device__ __forceinline__ int wave_inclusive_scan(int v)
+// inclusive prefix sum over the wave: row shifts, then the row broadcasts
+__device__ __forceinline__ int wave_incl_scan(int v)
 {
-    int lane = __lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
     return v;
 }
 
-// exclusive scan over the workgroup; s_w holds B/64 + 1 ints
+// Sum over the waves of the workgroup of per-wave values: returns the sum of
+// the waves before this one and sets *total.  s_w holds B/64 ints.
 template <int B>
-__device__ __forceinline__ int block_excl_scan(int v, int *s_w, int *total)
+__device__ __forceinline__ int waves_before(int wave_total, int *s_w, int *total)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int inc = wave_inclusive_scan(v);
-    if (lane == 63) s_w[w] = inc;
+    constexpr int NW = B / 64;
+    const int w = uni((int)(threadIdx.x >> 6));
+    if ((threadIdx.x & 63) == 0) s_w[w] = wave_total;
     lds_barrier();
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int i = 0; i < B / 64; ++i) {
-            int t = s_w[i];
-            s_w[i] = acc;
-            acc += t;
-        }
-        s_w[B / 64] = acc;
+    int before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+        const int t = s_w[i];
+        before += i < w ? t : 0;
+        all += t;
     }
-    lds_barrier();
-    int r = s_w[w] + inc - v;
-    *total = s_w[B / 64];
-    lds_barrier();
-    return r;
+    *total = all;
+    return before;
+}
+
+// Exclusive scan over the workgroup.  s_w holds 2 * (B/64) ints; the two
+// halves alternate with `phase` so back-to-back calls need one barrier each.
+template <int B>
+__device__ __forceinline__ int block_excl_scan(int v, int *s_w, int phase, int *total)
+{
+    const int inc = wave_incl_scan(v);
+    const int wt = __builtin_amdgcn_readlane(inc, 63);
+    if (B == 64) {
+        *total = wt;
+        return inc - v;
+    }
+    return waves_before<B>(wt, s_w + (phase & 1) * (B / 64), total) + inc - v;
+}
+
+// Exclusive counts of two predicates over the workgroup (ballots), packed as
+// count_a | count_b << 16 like the totals.
+template <int B>
+__device__ __forceinline__ int block_count2(bool pa, bool pb, int *s_w, int phase, int *total)
+{
+    const unsigned long long ma = __ballot(pa), mb = __ballot(pb);
+    const int mine = lane_rank(ma) | (lane_rank(mb) << 16);
+    const int wt = __popcll(ma) | (__popcll(mb) << 16);
+    if (B == 64) {
+        *total = wt;
+        return mine;
+    }
+    return waves_before<B>(wt, s_w + (phase & 1) * (B / 64), total) + mine;
 }
 
 // in-place exclusive scan of a[0..n) in LDS
@@ -240,7 +348,7 @@ __device__ void block_scan_inplace(int *a, int n, int *s_w)
     int sum = 0;
     for (int i = beg; i < end; ++i) sum += a[i];
     int total;
-    int off = block_excl_scan<B>(sum, s_w, &total);
+    int off = block_excl_scan<B>(sum, s_w, 0, &total);
     for (int i = beg; i < end; ++i) {
         int v = a[i];
         a[i] = off;
@@ -248,91 +356,83 @@ __device__ void block_scan_inplace(int *a, int n, int *s_w)
     }
 }
 
+// minimum over lanes lane ^ m, m = 1, 2, 4, 8 (quad permutes for 1 and 2)
+__device__ __forceinline__ int lane_xor(int v, int m)
+{
+    if (m == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    if (m == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    return __shfl_xor(v, m);
+}
+
+// ---------------------------------------------------------------- LDS layout
+// Dynamic LDS of one event workgroup, for a compile-time slot capacity CAP
+// (hits per module slot).  The sort scratch (histogram, fill counters, the
+// 32-bit sort keys and per-hit bins of events with at most sortcap/2 hits)
+// aliases the tracking area, which is filled only after the sort.
+//   ring   4 slots x CAP sorted hits (16 B each)
+//   tab    coarse phi index of each slot: first position whose phi16 high
+//          byte is >= b, b = 0..256
+//   freel  unflagged positions of the seeding stage's doublet module
+//   freem  unflagged positions of the middle module
+//   frank  unflagged positions before each doublet-module position
+//   al0/1  active-track lists (CAP entries; more sends the event to memory)
+//   res    per active slot: best hit id | window position << 16, scatter
+//   own    hit-flag bitmap of the event when N <= own_cap
+extern __shared__ __align__(16) char g_lds[];
+
+constexpr int kTab = 257;
+__host__ __device__ constexpr uint32_t a16(uint32_t v) { return (v + 15u) & ~15u; }
+__host__ __device__ constexpr uint32_t lay_tab(int cap) { return 64u * (uint32_t)cap; }
+__host__ __device__ constexpr uint32_t lay_freel(int cap) { return a16(lay_tab(cap) + 8u * kTab); }
+__host__ __device__ constexpr uint32_t lay_freem(int cap) { return lay_freel(cap) + a16(2u * cap); }
+__host__ __device__ constexpr uint32_t lay_frank(int cap) { return lay_freem(cap) + a16(2u * cap); }
+__host__ __device__ constexpr uint32_t lay_al0(int cap) { return lay_frank(cap) + a16(2u * cap); }
+__host__ __device__ constexpr uint32_t lay_al1(int cap) { return lay_al0(cap) + a16(2u * cap); }
+__host__ __device__ constexpr uint32_t lay_res(int cap) { return lay_al1(cap) + a16(2u * cap); }
+__host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_res(cap) + 8u * cap; }
+
 // sort bins: 1024 in total, a power of two per module
 constexpr int kSortBins = 1024;
-__host__ __device__ __forceinline__ int sort_shift(int M)
+__host__ __device__ constexpr uint32_t lds_sort_head() { return a16((2u * kSortBins + 1u) * 4u); }
+
+__host__ __device__ inline uint32_t lds_bytes(int cap, int own_cap)
+{
+    const uint32_t sort = lds_sort_head() + 4u * 1024u;   // keys of 1,024 hits at least
+    const uint32_t track = cap > 0 ? lay_own(cap) + a16(4u * (uint32_t)((own_cap + 31) / 32)) : 0u;
+    return sort > track ? sort : track;
+}
+__host__ __device__ inline int lds_sortcap(int cap, int own_cap)
+{
+    return (int)((lds_bytes(cap, own_cap) - lds_sort_head()) / 4u);
+}
+
+__host__ __device__ inline int sort_shift(int M)
 {
     int bits = 4;                       // M <= 64 -> at least 16 bins per module
     while (bits < 12 && (M << (bits + 1)) <= kSortBins) ++bits;
     return 16 - bits;
 }
 
-// Dynamic LDS of one event workgroup.  The sort scratch (histogram, fill
-// counters and the 32-bit sort keys of events with at most sortcap hits)
-// aliases the module ring, which is filled only after the sort.
-//   ring  4 slots x cap hits: phi16, id, x, y, z (16 B per hit)
-//   freel unflagged positions of the seeding stage's doublet module
-//   frank rank of each doublet-module position among its unflagged positions
-//   tab   coarse phi index of each slot
-//   al0/al1, sbest, sbsc  active-track lists and per-stage search results of
-//         the first cap active tracks (the rest live in memory)
-//   own   hit-flag bitmap of the event when N <= own_cap
-struct Lds {
-    int cap, own_cap, sortcap;
-    uint32_t *keys;
-    uint16_t *rq, *rid;
-    float *rx, *ry, *rz;
-    uint16_t *freel;     // unflagged positions of the doublet module (cap entries)
-    uint16_t *freem;     // unflagged positions of the middle module (cap entries)
-    uint16_t *frank;     // unflagged positions before each doublet-module position
-    uint16_t *tab;       // per slot: first position whose phi16 high byte is >= b, b = 0..256
-    uint16_t *al0, *al1; // active track lists (first cap entries)
-    uint32_t *sbest;     // per active slot: best hit id | window position << 16
-    float *sbsc;         // per active slot: its scatter
-    uint32_t *own;
-    int *hist, *fill;
+template <int CAP>
+struct Lay {
+    static __device__ __forceinline__ Hit16 *ring(int s) { return reinterpret_cast<Hit16 *>(g_lds) + s * CAP; }
+    static __device__ __forceinline__ uint16_t *tab(int s)
+    {
+        return reinterpret_cast<uint16_t *>(g_lds + lay_tab(CAP)) + s * kTab;
+    }
+    static __device__ __forceinline__ uint16_t *freel() { return reinterpret_cast<uint16_t *>(g_lds + lay_freel(CAP)); }
+    static __device__ __forceinline__ uint16_t *freem() { return reinterpret_cast<uint16_t *>(g_lds + lay_freem(CAP)); }
+    static __device__ __forceinline__ uint16_t *frank() { return reinterpret_cast<uint16_t *>(g_lds + lay_frank(CAP)); }
+    static __device__ __forceinline__ uint16_t *al(int i)
+    {
+        return reinterpret_cast<uint16_t *>(g_lds + (i ? lay_al1(CAP) : lay_al0(CAP)));
+    }
+    static __device__ __forceinline__ unsigned long long *res()
+    {
+        return reinterpret_cast<unsigned long long *>(g_lds + lay_res(CAP));
+    }
+    static __device__ __forceinline__ uint32_t *own() { return reinterpret_cast<uint32_t *>(g_lds + lay_own(CAP)); }
 };
-
-__host__ __device__ __forceinline__ size_t lds_align(size_t v) { return (v + 15) & ~size_t(15); }
-
-constexpr int kTab = 257;
-
-__host__ __device__ __forceinline__ size_t lds_ring_bytes(int cap)
-{
-    return lds_align((size_t)4 * cap * 16) + 5 * lds_align((size_t)cap * 2) + lds_align((size_t)4 * kTab * 2) +
-           2 * lds_align((size_t)cap * 4);
-}
-
-__host__ __device__ __forceinline__ size_t lds_sort_head() { return lds_align((size_t)(2 * kSortBins + 1) * 4); }
-
-__host__ __device__ __forceinline__ size_t lds_bytes(int cap, int own_cap)
-{
-    const size_t sort = lds_sort_head() + 4 * 1024;   // room for the keys of 1,024 hits at least
-    const size_t track = lds_ring_bytes(cap) + lds_align((size_t)((own_cap + 31) / 32) * 4);
-    return sort > track ? sort : track;
-}
-
-__device__ __forceinline__ Lds carve_lds(char *base, int cap, int own_cap)
-{
-    Lds L;
-    L.cap = cap;
-    L.own_cap = own_cap;
-    L.sortcap = (int)((lds_bytes(cap, own_cap) - lds_sort_head()) / 4);
-    L.keys = (uint32_t *)(base + lds_sort_head());
-    const int c4 = 4 * cap;
-    L.rx = (float *)base;
-    L.ry = L.rx + c4;
-    L.rz = L.ry + c4;
-    L.rq = (uint16_t *)(L.rz + c4);
-    L.rid = L.rq + c4;
-    L.freel = (uint16_t *)(base + lds_align((size_t)4 * cap * 16));
-    L.freem = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + lds_align((size_t)cap * 2));
-    L.frank = (uint16_t *)(base + lds_align((size_t)4 * cap * 16) + 2 * lds_align((size_t)cap * 2));
-    char *p = base + lds_align((size_t)4 * cap * 16) + 3 * lds_align((size_t)cap * 2);
-    L.tab = (uint16_t *)p;
-    p += lds_align((size_t)4 * kTab * 2);
-    L.al0 = (uint16_t *)p;
-    p += lds_align((size_t)cap * 2);
-    L.al1 = (uint16_t *)p;
-    p += lds_align((size_t)cap * 2);
-    L.sbest = (uint32_t *)p;
-    p += lds_align((size_t)cap * 4);
-    L.sbsc = (float *)p;
-    L.own = (uint32_t *)(base + lds_ring_bytes(cap));
-    L.hist = (int *)base;
-    L.fill = L.hist + kSortBins + 1;
-    return L;
-}
 
 // static LDS shared by the stages of one event
 template <int B>
@@ -341,10 +441,65 @@ struct Shared {
     int cnt[4];          // records, list[0], list[1], final
     int status;
     int e;
-    int scan[B / 64 + 1];
-    int slot_n[4];       // hits of the module held by each ring slot
     int maxmod;          // hits of the event's largest module
+    int ovf;             // an LDS list overflowed
+    int scan[2 * (B / 64)];
+    int slot_n[4];       // hits of the module held by each ring slot
 };
+
+// per-event views of the workspace: pointers are derived on use from the
+// base, the capacity H and the event's hit offset hb
+struct Ev {
+    char *base;
+    uint32_t H, E;
+    int e, hb, N;
+    template <class T>
+    __device__ __forceinline__ T *arr(uint32_t off, uint32_t elem) const
+    {
+        return reinterpret_cast<T *>(base + (uint64_t)H * off + (uint64_t)(uint32_t)hb * elem);
+    }
+    __device__ __forceinline__ Rec *rec() const { return arr<Rec>(kOffRec, 32); }
+    __device__ __forceinline__ Hit16 *hs() const { return arr<Hit16>(kOffHs, 16); }
+    __device__ __forceinline__ RecAux *aux() const { return arr<RecAux>(kOffAux, 16); }
+    __device__ __forceinline__ unsigned long long *claim() const { return arr<unsigned long long>(kOffClaim, 8); }
+    __device__ __forceinline__ uint32_t *keys() const { return arr<uint32_t>(kOffKeys, 4); }
+    __device__ __forceinline__ uint16_t *link() const { return arr<uint16_t>(kOffLink, 4); }   // [2i] prev, [2i+1] key -> record
+    __device__ __forceinline__ int32_t *st_toff() const { return arr<int32_t>(kOffToff, 4); }
+    __device__ __forceinline__ uint16_t *st_hits() const { return arr<uint16_t>(kOffStHits, 2); }
+    __device__ __forceinline__ uint16_t *list(int k) const
+    {
+        return reinterpret_cast<uint16_t *>(base + (uint64_t)H * (kOffLists + 2u * k) + (uint64_t)(uint32_t)hb * 2);
+    }
+    __device__ __forceinline__ uint32_t *own() const
+    {
+        return reinterpret_cast<uint32_t *>(base + ws_owner(H)) + ((uint32_t)hb >> 5) + e;
+    }
+    __device__ __forceinline__ EvInfo &info() const
+    {
+        return reinterpret_cast<EvInfo *>(base + ws_ev(H, E))[e];
+    }
+};
+
+__device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N)
+{
+    Ev v;
+    v.base = opq(W.base);
+    v.H = opq(W.H);
+    v.E = W.E;
+    v.e = e;
+    v.hb = hb;
+    v.N = N;
+    return v;
+}
+
+// the view with its base hidden from the optimiser (see opq)
+__device__ __forceinline__ Ev fresh(const Ev &v)
+{
+    Ev w = v;
+    w.base = opq(v.base);
+    w.H = opq(v.H);
+    return w;
+}
 
 // ---------------------------------------------------------------- validation
 // Loads the event-local module offsets into LDS and checks the offsets.
@@ -385,49 +540,69 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
 // Counting sort on (module, top bits of phi16) into buckets of 32-bit keys
 // phi16 << 16 | id, then each key's rank inside its bucket by counting the
 // smaller keys of the bucket; ties in phi16 fall to the lower id because the
-// id is the key's low half.
+// id is the key's low half.  Keys and per-hit bins live in LDS when the
+// event has at most sortcap/2 hits, else in memory.
 template <int B>
-__device__ void stage_sort(const sbt_params &P, const HitsArgs &H, const Work &W, int hb, int N,
-                           Shared<B> &S, const Lds &L)
+__device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0, Shared<B> &S, int sortcap)
 {
-    const int M = P.n_modules;
+    const Ev v = fresh(v0);
+    const int M = fresh(PP).M, N = v.N;
     const int shift = sort_shift(M);
     const int bpm = 1 << (16 - shift);
     const int nb = M * bpm;
-    int *hist = L.hist, *fill = L.fill;
-    uint32_t *keys = N <= L.sortcap ? L.keys : W.keys + hb;
+    int *hist = reinterpret_cast<int *>(g_lds);
+    int *fill = hist + kSortBins + 1;
+    uint32_t *lkeys = reinterpret_cast<uint32_t *>(g_lds + lds_sort_head());
+    const bool in_lds = 2 * N <= sortcap;
     for (int i = threadIdx.x; i <= nb; i += B) hist[i] = 0;
     for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
     __syncthreads();
-    const float *__restrict__ X = H.x + hb;
-    const float *__restrict__ Y = H.y + hb;
-    const float *__restrict__ Z = H.z + hb;
+    const float *__restrict__ X = H.x + v.hb;
+    const float *__restrict__ Y = H.y + v.hb;
+    const float *__restrict__ Z = H.z + v.hb;
+    // bins: LDS after the keys, or the claim words (not yet in use) in memory
+    uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
     for (int i = threadIdx.x; i < N; i += B) {
-        const uint16_t qi = phi16(X[i], Y[i]);
-        atomicAdd(&hist[module_of(S.mo, M, i) * bpm + (qi >> shift)], 1);
+        const uint16_t qi = phi16(at(X, i), at(Y, i));
+        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
+        const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
+        if (in_lds) lkeys[N + i] = tb;
+        else at(bins_m, i) = tb;
+        atomicAdd(&hist[bin], 1);
     }
     __syncthreads();
     block_scan_inplace<B>(hist, nb + 1, S.scan);
     __syncthreads();
-    for (int i = threadIdx.x; i < N; i += B) {
-        const uint16_t qi = phi16(X[i], Y[i]);
-        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
-        keys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < N; i += B) {
+            const uint32_t tb = lkeys[N + i];
+            const int bin = (int)(tb >> 16);
+            lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = (tb << 16) | (uint32_t)i;
+        }
+    } else {
+        for (int i = threadIdx.x; i < N; i += B) {
+            const uint32_t tb = at(bins_m, i);
+            const int bin = (int)(tb >> 16);
+            at(v.keys(), hist[bin] + atomicAdd(&fill[bin], 1)) = (tb << 16) | (uint32_t)i;
+        }
     }
     __syncthreads();
     for (int s = threadIdx.x; s < N; s += B) {
-        const uint32_t key = keys[s];
+        const uint32_t key = in_lds ? lkeys[s] : at(v.keys(), s);
         const int i = (int)(key & 0xFFFFu);
-        const uint16_t qi = (uint16_t)(key >> 16);
-        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
+        const int bin = (int)((in_lds ? lkeys[N + i] : at(bins_m, i)) >> 16);
         const int lo = hist[bin], hi = hist[bin + 1];
         int rank = lo;
-        for (int m = lo; m < hi; ++m) rank += keys[m] < key;
-        W.sx[hb + rank] = X[i];
-        W.sy[hb + rank] = Y[i];
-        W.sz[hb + rank] = Z[i];
-        W.sq[hb + rank] = qi;
-        W.sid[hb + rank] = (uint16_t)i;
+        if (in_lds)
+            for (int m = lo; m < hi; ++m) rank += lkeys[m] < key;
+        else
+            for (int m = lo; m < hi; ++m) rank += at(v.keys(), m) < key;
+        Hit16 h;
+        h.x = at(X, i);
+        h.y = at(Y, i);
+        h.z = at(Z, i);
+        h.qid = (key >> 16) | (key << 16);
+        at(v.hs(), rank) = h;
     }
     __syncthreads();
 }
@@ -437,44 +612,50 @@ __device__ void stage_sort(const sbt_params &P, const HitsArgs &H, const Work &W
 // LDS bitmap) runs the LDS instantiation of the tracking stages: traversal
 // index u lives in ring slot u & 3 and every window access is an LDS access.
 // Any other event runs the memory instantiation, which reads the sorted
-// arrays in memory directly.  Both compute the same thing.
+// hits in memory directly.  Both compute the same thing.
 struct Win {
-    const uint16_t *q, *id;
-    const float *x, *y, *z;
+    const Hit16 *h;
     const uint16_t *tab;   // coarse index (LDS instantiation)
     int n;
 };
+
+__device__ __forceinline__ uint16_t q_of(const Hit16 &h) { return (uint16_t)(h.qid & 0xFFFFu); }
+__device__ __forceinline__ uint16_t id_of(const Hit16 &h) { return (uint16_t)(h.qid >> 16); }
+__device__ __forceinline__ uint16_t win_q(const Win &w, int p) { return (uint16_t)(at(w.h, p).qid & 0xFFFFu); }
+__device__ __forceinline__ uint16_t win_id(const Win &w, int p) { return (uint16_t)(at(w.h, p).qid >> 16); }
 
 // first position of the window whose phi16 is >= v
 template <bool kLds>
 __device__ __forceinline__ int win_lower_bound(const Win &w, uint16_t v)
 {
     if (kLds) {
-        int p = w.tab[v >> 8];
-        const int end = w.tab[(v >> 8) + 1];
-        while (p < end && w.q[p] < v) ++p;
+        int p = at(w.tab, v >> 8);
+        const int end = at(w.tab, (v >> 8) + 1);
+        while (p < end && win_q(w, p) < v) ++p;
         return p;
     }
-    return lower_bound16(w.q, w.n, v);
+    int lo = 0, hi = w.n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (win_q(w, mid) < v) lo = mid + 1; else hi = mid;
+    }
+    return lo;
 }
 
-template <int B, bool kLds>
-__device__ __forceinline__ Win window(const sbt_params &P, const Lds &L, const Shared<B> &S, const Work &W, int hb,
-                                      int u)
+template <int B, bool kLds, int CAP>
+__device__ __forceinline__ Win window(const Prm &P, const Shared<B> &S, const Ev &v, int u)
 {
     Win w;
     if (kLds) {
         const int s = u & 3;
-        const int o = s * L.cap;
         w.n = uni(S.slot_n[s]);
-        w.q = L.rq + o; w.id = L.rid + o; w.x = L.rx + o; w.y = L.ry + o; w.z = L.rz + o;
-        w.tab = L.tab + s * kTab;
+        w.h = Lay<CAP>::ring(s);
+        w.tab = Lay<CAP>::tab(s);
     } else {
         const int k = kmod(P, u);
         const int g0 = uni(S.mo[k]);
         w.n = uni(S.mo[k + 1]) - g0;
-        const int g = hb + g0;
-        w.q = W.sq + g; w.id = W.sid + g; w.x = W.sx + g; w.y = W.sy + g; w.z = W.sz + g;
+        w.h = v.hs() + g0;
         w.tab = nullptr;
     }
     return w;
@@ -484,8 +665,8 @@ __device__ __forceinline__ Win window(const sbt_params &P, const Lds &L, const S
 template <int B>
 struct RingStage {
     static constexpr int PF = (512 + B - 1) / B;
-    uint16_t q[PF], qp[PF], id[PF];
-    float x[PF], y[PF], z[PF];
+    Hit16 h[PF];
+    uint16_t qp[PF];
 };
 
 // coarse-index entries owned by position i of an n-hit slot whose phi16 is
@@ -502,73 +683,49 @@ __device__ __forceinline__ void tab_fill(uint16_t *tab, int i, int n, uint16_t q
 }
 
 template <int B>
-__device__ __forceinline__ void ring_load(const sbt_params &P, const Work &W, int hb, int u, const Shared<B> &S,
-                                          const Lds &L, RingStage<B> &R)
+__device__ __forceinline__ void ring_load(const Prm &P, const Ev &v, int u, const Shared<B> &S,
+                                          RingStage<B> &R)
 {
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
+    const Hit16 *src = v.hs() + g;
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
-            R.q[j] = W.sq[hb + g + i];
-            R.qp[j] = i > 0 ? W.sq[hb + g + i - 1] : (uint16_t)0;
-            R.id[j] = W.sid[hb + g + i];
-            R.x[j] = W.sx[hb + g + i];
-            R.y[j] = W.sy[hb + g + i];
-            R.z[j] = W.sz[hb + g + i];
+            R.h[j] = at(src, i);
+            R.qp[j] = i > 0 ? q_of(at(src, i - 1)) : (uint16_t)0;
         }
     }
 }
 
-template <int B>
-__device__ __forceinline__ void ring_store(const sbt_params &P, const Work &W, int hb, int u, Shared<B> &S,
-                                           const Lds &L, const RingStage<B> &R)
+template <int B, int CAP>
+__device__ __forceinline__ void ring_store(const Prm &P, const Ev &v, int u, Shared<B> &S,
+                                           const RingStage<B> &R)
 {
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
     const int s = u & 3;
     if (threadIdx.x == 0) S.slot_n[s] = n;
-    const int o = s * L.cap;
-    uint16_t *tab = L.tab + s * kTab;
+    Hit16 *ring = Lay<CAP>::ring(s);
+    uint16_t *tab = Lay<CAP>::tab(s);
     if (n == 0)
         for (int b = threadIdx.x; b < kTab; b += B) tab[b] = 0;
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
-            L.rq[o + i] = R.q[j];
-            L.rid[o + i] = R.id[j];
-            L.rx[o + i] = R.x[j];
-            L.ry[o + i] = R.y[j];
-            L.rz[o + i] = R.z[j];
-            tab_fill(tab, i, n, R.q[j], R.qp[j]);
+            ring[i] = R.h[j];
+            tab_fill(tab, i, n, q_of(R.h[j]), R.qp[j]);
         }
     }
+    const Hit16 *src = v.hs() + g;
     for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {
-        const uint16_t q = W.sq[hb + g + i];
-        L.rq[o + i] = q;
-        L.rid[o + i] = W.sid[hb + g + i];
-        L.rx[o + i] = W.sx[hb + g + i];
-        L.ry[o + i] = W.sy[hb + g + i];
-        L.rz[o + i] = W.sz[hb + g + i];
-        tab_fill(tab, i, n, q, W.sq[hb + g + i - 1]);
+        const Hit16 h = at(src, i);
+        ring[i] = h;
+        tab_fill(tab, i, n, q_of(h), q_of(at(src, i - 1)));
     }
 }
-
-// ---------------------------------------------------------------- active lists
-// A list of record indices whose first cap entries live in LDS and the rest
-// in memory (cap = 0 in the memory instantiation).
-struct AList {
-    uint16_t *lds, *mem;
-    int cap;
-    __device__ __forceinline__ uint16_t get(int a) const { return a < cap ? lds[a] : mem[a]; }
-    __device__ __forceinline__ void put(int a, uint16_t v) const
-    {
-        if (a < cap) lds[a] = v;
-        else mem[a] = v;
-    }
-};
 
 // ---------------------------------------------------------------- seeding
 // The pendulum search visits the doublet module's phi-sorted positions in
@@ -586,7 +743,7 @@ __device__ __forceinline__ int pendulum_pick(const uint16_t *F, int nf, int j, i
         if (su < nf) {
             int ix = j + su;
             if (ix >= nf) ix -= nf;
-            pu = F[ix];
+            pu = at(F, ix);
             int o = pu - s0;
             if (o < 0) o += na;
             if (o <= hu) vu = 2 * o;
@@ -594,7 +751,7 @@ __device__ __forceinline__ int pendulum_pick(const uint16_t *F, int nf, int j, i
         if (sd < nf) {
             int ix = j - 1 - sd;
             if (ix < 0) ix += nf;
-            pd = F[ix];
+            pd = at(F, ix);
             int o = s0 - pd;
             if (o < 0) o += na;
             if (o >= 1 && o <= hd) vd = 2 * o - 1;
@@ -606,33 +763,20 @@ __device__ __forceinline__ int pendulum_pick(const uint16_t *F, int nf, int j, i
     return pos;
 }
 
-// best third hit for one doublet (h0 at wa position pos, h1 = middle hit)
-struct SeedBest {
-    float sc;
-    uint16_t id0, id2;
-    int pos0, pos2;
-    bool found;
-};
-
-__device__ __forceinline__ bool seed_better(const SeedBest &a, const SeedBest &b)
-{
-    if (a.found != b.found) return a.found;
-    if (!a.found) return false;
-    if (a.sc != b.sc) return a.sc < b.sc;
-    if (a.id0 != b.id0) return a.id0 < b.id0;
-    return a.id2 < b.id2;
-}
-
+// Best third hit for one doublet: the key orders like the comparison
+// (found, scatter, id0, id2) -- scatter bits << 32 | id0 << 16 | id2, ~0 when
+// nothing was found (scatters are >= +0, so their bits order like the
+// values); pos holds the window positions pos0 | pos2 << 16.
 template <bool kLds>
 __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const uint32_t *own, int pos0, float x1,
                                              float y1, float z1, float Zc, float Ss, uint16_t Ws, uint16_t span,
-                                             SeedBest &b)
+                                             unsigned long long &bkey, uint32_t &bpos)
 {
-    const uint16_t id0 = wa.id[pos0];
-    const float x0 = wa.x[pos0], y0 = wa.y[pos0], z0 = wa.z[pos0];
-    const float d01 = z1 - z0;
-    const float tx = (x1 - x0) / d01;
-    const float ty = (y1 - y0) / d01;
+    const Hit16 h0 = at(wa.h, pos0);
+    const uint16_t id0 = id_of(h0);
+    const float d01 = z1 - h0.z;
+    const float tx = (x1 - h0.x) / d01;
+    const float ty = (y1 - h0.y) / d01;
     const float dzc = Zc - z1;
     const uint16_t qe = phi16(x1 + tx * dzc, y1 + ty * dzc);
     const int nc = wc.n;
@@ -643,22 +787,20 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
     for (int jj = 0; jj < nc; ++jj) {
         int pc = st + jj;
         if (pc >= nc) pc -= nc;
-        const uint16_t qc = wc.q[pc];
-        if ((uint16_t)(qc - lo) > span) break;
-        const uint16_t id2 = wc.id[pc];
+        const Hit16 h2 = at(wc.h, pc);
+        if ((uint16_t)(q_of(h2) - lo) > span) break;
+        const uint16_t id2 = id_of(h2);
         if (!is_free(own, id2)) continue;
-        const float dz = wc.z[pc] - z1;
-        const float dx = (x1 + tx * dz) - wc.x[pc];
-        const float dy = (y1 + ty * dz) - wc.y[pc];
+        const float dz = h2.z - z1;
+        const float dx = (x1 + tx * dz) - h2.x;
+        const float dy = (y1 + ty * dz) - h2.y;
         const float sc = (dx * dx) + (dy * dy);
         if (!(sc < Ss)) continue;
-        if (!b.found || sc < b.sc || (sc == b.sc && (id0 < b.id0 || (id0 == b.id0 && id2 < b.id2)))) {
-            b.found = true;
-            b.sc = sc;
-            b.id0 = id0;
-            b.id2 = id2;
-            b.pos0 = pos0;
-            b.pos2 = pc;
+        const unsigned long long k =
+            ((unsigned long long)__float_as_uint(sc) << 32) | ((uint32_t)id0 << 16) | id2;
+        if (k < bkey) {
+            bkey = k;
+            bpos = (uint32_t)pos0 | ((uint32_t)pc << 16);
         }
     }
 }
@@ -671,17 +813,17 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
 // three seed hits of a bare seed) keyed (scatter, key) for stage u.
 // Returns the best hit's id | window position << 16, or ~0.
 template <bool kLds>
-__device__ __forceinline__ uint32_t follow_item(const sbt_params &P, const Win &wc, float Zc, const uint32_t *own,
+__device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, float Zc, const uint32_t *own,
                                                 unsigned long long *claim, const Rec &R, int u, float &bsc_out)
 {
-    const float Sf = P.max_scatter_forwarding;
-    const uint16_t Wf = (uint16_t)P.phi_window_forwarding;
-    const uint16_t span = (uint16_t)(2 * P.phi_window_forwarding);
+    const float Sf = P.Sf;
+    const uint16_t Wf = (uint16_t)P.Wf;
+    const uint16_t span = (uint16_t)(2 * P.Wf);
     const int nc = wc.n;
     uint16_t best = kNone;
     int bpos = 0;
     float bsc = 0.0f;
-    bool elig = (u - (int)R.last_t) <= P.max_consecutive_misses + 1;
+    bool elig = (u - (int)R.last_t) <= P.misses + 1;
     if (elig && R.len == 3) elig = is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2);
     if (elig && nc > 0) {
         const float dzc = Zc - R.zb;
@@ -692,13 +834,13 @@ __device__ __forceinline__ uint32_t follow_item(const sbt_params &P, const Win &
         for (int j = 0; j < nc; ++j) {
             int pc = st + j;
             if (pc >= nc) pc -= nc;
-            const uint16_t qc = wc.q[pc];
-            if ((uint16_t)(qc - lo) > span) break;
-            const uint16_t id = wc.id[pc];
+            const Hit16 h = at(wc.h, pc);
+            if ((uint16_t)(q_of(h) - lo) > span) break;
+            const uint16_t id = id_of(h);
             if (!is_free(own, id)) continue;
-            const float dz = wc.z[pc] - R.zb;
-            const float dx = (R.xb + R.tx * dz) - wc.x[pc];
-            const float dy = (R.yb + R.ty * dz) - wc.y[pc];
+            const float dz = h.z - R.zb;
+            const float dx = (R.xb + R.tx * dz) - h.x;
+            const float dy = (R.yb + R.ty * dz) - h.y;
             const float sc = (dx * dx) + (dy * dy);
             if (!(sc < Sf)) continue;
             if (best == kNone || sc < bsc || (sc == bsc && id < best)) {
@@ -709,11 +851,11 @@ __device__ __forceinline__ uint32_t follow_item(const sbt_params &P, const Win &
         }
         if (best != kNone) {
             const unsigned long long kap = claim_key(bsc, R.key, u);
-            atomicMin(&claim[best], kap);
+            atomicMin(&at(claim, best), kap);
             if (R.len == 3) {
-                atomicMin(&claim[R.h0], kap);
-                atomicMin(&claim[R.h1], kap);
-                atomicMin(&claim[R.h2], kap);
+                atomicMin(&at(claim, R.h0), kap);
+                atomicMin(&at(claim, R.h1), kap);
+                atomicMin(&at(claim, R.h2), kap);
             }
         }
     }
@@ -721,16 +863,31 @@ __device__ __forceinline__ uint32_t follow_item(const sbt_params &P, const Win &
     return best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
 }
 
-// search result of active slot a (record r): LDS for the first cap slots
-__device__ __forceinline__ void put_result(const Lds &L, const Work &W, int hb, int cap, int a, int r, uint32_t pb,
-                                           float bsc)
+// search result of active slot a (record r): LDS slot in the LDS
+// instantiation, the record's auxiliary data in the memory one
+template <bool kLds, int CAP>
+__device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t pb, float bsc)
 {
-    if (a < cap) {
-        L.sbest[a] = pb;
-        L.sbsc[a] = bsc;
+    if (kLds) {
+        Lay<CAP>::res()[a] = (unsigned long long)pb | ((unsigned long long)__float_as_uint(bsc) << 32);
     } else {
-        W.rbest[hb + r] = pb;
-        W.rbsc[hb + r] = bsc;
+        RecAux &x = at(v.aux(), r);
+        x.best = pb;
+        x.bsc = bsc;
+    }
+}
+
+template <bool kLds, int CAP>
+__device__ __forceinline__ void get_result(const Ev &v, int a, int r, uint32_t &pb, float &bsc)
+{
+    if (kLds) {
+        const unsigned long long w = Lay<CAP>::res()[a];
+        pb = (uint32_t)w;
+        bsc = __uint_as_float((uint32_t)(w >> 32));
+    } else {
+        const RecAux &x = at(v.aux(), r);
+        pb = x.best;
+        bsc = x.bsc;
     }
 }
 
@@ -738,51 +895,57 @@ __device__ __forceinline__ void put_result(const Lds &L, const Work &W, int hb, 
 // t+1.  Seeding: modules A = kmod(t-2), Bm = kmod(t-1), C = kmod(t); work
 // items are (unflagged middle hit, partner rank c) -- with K a power of two
 // up to 16, the K doublets of a middle hit run on K adjacent lanes and their
-// best triplets are reduced with lane shuffles, otherwise one lane handles
-// all K.  A new seed's following search into t+1 runs on the lane that made
-// it.  The tracks kept by the last resolution (active slots [0, n_keep))
-// search t+1 on waves of their own.  Both read the flags as the resolution
-// of t left them, which is the state the following of t+1 starts from.
-template <int B, bool kLds>
-__device__ void stage_seed_follow(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S, const Lds &L,
-                                  const uint32_t *own, const AList &nxt, int *n_nxt, int n_keep, bool follow_next)
+// best triplets are reduced across the lanes, otherwise one lane handles all
+// K.  A new seed's following search into t+1 runs on the lane that made it.
+// The tracks kept by the last resolution (active slots [0, n_keep)) search
+// t+1 on waves of their own.  Both read the flags as the resolution of t
+// left them, which is the state the following of t+1 starts from.
+template <int B, bool kLds, int CAP>
+__device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Shared<B> &S, const uint32_t *own,
+                                  uint16_t *nxt, int *n_nxt, int n_keep, bool follow_next)
 {
-    const Win wa = window<B, kLds>(P, L, S, W, hb, t - 2);
-    const Win wb = window<B, kLds>(P, L, S, W, hb, t - 1);
-    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
+    const Prm P = fresh(PP);
+    const Ev v = fresh(v0);
+    const Win wa = window<B, kLds, CAP>(P, S, v, t - 2);
+    const Win wb = window<B, kLds, CAP>(P, S, v, t - 1);
+    const Win wc = window<B, kLds, CAP>(P, S, v, t);
     Win wn = wc;
     float Zn = 0.0f;
     if (follow_next) {
-        wn = window<B, kLds>(P, L, S, W, hb, t + 1);
-        Zn = P.module_z[kmod(P, t + 1)];
+        wn = window<B, kLds, CAP>(P, S, v, t + 1);
+        Zn = PP.module_z[kmod(P, t + 1)];
     }
-    unsigned long long *__restrict__ claim = W.claim + hb;
     const int na = wa.n, nbm = wb.n;
-    const float Zc = P.module_z[kmod(P, t)];
-    const float Ss = P.max_scatter_seeding;
-    const int K = P.max_doublet_candidates;
-    const uint16_t Ws = (uint16_t)P.phi_window_seeding;
-    const uint16_t span = (uint16_t)(2 * P.phi_window_seeding);
+    const float Zc = PP.module_z[kmod(P, t)];
+    const float Ss = P.Ss;
+    const int K = P.K;
+    const uint16_t Ws = (uint16_t)P.Ws;
+    const uint16_t span = (uint16_t)(2 * P.Ws);
 
     // unflagged positions of the doublet module and of the middle module, ascending
     uint16_t *F, *FR, *FM;
     if (kLds) {
-        F = L.freel; FR = L.frank; FM = L.freem;
+        F = Lay<CAP>::freel();
+        FR = Lay<CAP>::frank();
+        FM = Lay<CAP>::freem();
     } else {
-        const int ga = hb + uni(S.mo[kmod(P, t - 2)]), gb = hb + uni(S.mo[kmod(P, t - 1)]);
-        F = W.freel + ga; FR = W.frank + ga; FM = W.freem + gb;
+        const int ga = uni(S.mo[kmod(P, t - 2)]), gb = uni(S.mo[kmod(P, t - 1)]);
+        F = v.list(kListFreeL) + ga;
+        FR = v.list(kListFRank) + ga;
+        FM = v.list(kListFreeM) + gb;
     }
     int nf = 0, nfm = 0;
     const int nmax = na > nbm ? na : nbm;
-    for (int base = 0; base < nmax; base += B) {
+    int phase = 0;
+    for (int base = 0; base < nmax; base += B, ++phase) {
         const int p = base + (int)threadIdx.x;
-        const bool fa = p < na && is_free(own, wa.id[p]);
-        const bool fb = p < nbm && is_free(own, wb.id[p]);
+        const bool fa = p < na && is_free(own, win_id(wa, p));
+        const bool fb = p < nbm && is_free(own, win_id(wb, p));
         int total;
-        const int idx = block_excl_scan<B>((fa ? 1 : 0) | (fb ? 0x10000 : 0), S.scan, &total);
-        if (p < na) FR[p] = (uint16_t)(nf + (idx & 0xFFFF));
-        if (fa) F[nf + (idx & 0xFFFF)] = (uint16_t)p;
-        if (fb) FM[nfm + (idx >> 16)] = (uint16_t)p;
+        const int idx = block_count2<B>(fa, fb, S.scan, phase, &total);
+        if (p < na) at(FR, p) = (uint16_t)(nf + (idx & 0xFFFF));
+        if (fa) at(F, nf + (idx & 0xFFFF)) = (uint16_t)p;
+        if (fb) at(FM, nfm + (idx >> 16)) = (uint16_t)p;
         nf += total & 0xFFFF;
         nfm += total >> 16;
     }
@@ -803,75 +966,76 @@ __device__ void stage_seed_follow(const sbt_params &P, const Work &W, int hb, in
         if (g_wave >= seed_pad) {
             const int a = g - seed_pad;
             if (a < follow_items) {
-                const int r = nxt.get(a);
-                const Rec R = W.rec[hb + r];
+                const int r = at(nxt, a);
+                const Rec R = at(v.rec(), r);
                 float bsc;
-                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, claim, R, t + 1, bsc);
-                put_result(L, W, hb, nxt.cap, a, r, pb, bsc);
+                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
+                put_result<kLds, CAP>(v, a, r, pb, bsc);
             }
             continue;
         }
         const int i = g / G, c = g - i * G;
-        SeedBest best;
-        best.found = false;
-        best.sc = 0.0f;
-        best.id0 = kNone;
-        best.id2 = kNone;
-        best.pos0 = 0;
-        best.pos2 = 0;
-        int p1 = 0;
-        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f;
+        unsigned long long bkey = ~0ull;
+        uint32_t bpos = 0;
+        Hit16 h1;
+        h1.x = h1.y = h1.z = 0.0f;
+        h1.qid = 0;
         if (g < seed_items) {
-            p1 = FM[i];
-            x1 = wb.x[p1]; y1 = wb.y[p1]; z1 = wb.z[p1];
-            int s0 = win_lower_bound<kLds>(wa, wb.q[p1]);
+            const int p1 = at(FM, i);
+            h1 = at(wb.h, p1);
+            int s0 = win_lower_bound<kLds>(wa, q_of(h1));
             if (s0 == na) s0 = 0;
-            const int j = FR[s0];   // first unflagged position >= s0, as an index into F
+            const int j = at(FR, s0);   // first unflagged position >= s0, as an index into F
             for (int cc = 0; cc < per_lane; ++cc) {
                 const int pos0 = pendulum_pick(F, nf, j, s0, na, hu, hd, c + cc);
                 if (pos0 < 0) break;
-                seed_doublet<kLds>(wa, wc, own, pos0, x1, y1, z1, Zc, Ss, Ws, span, best);
+                seed_doublet<kLds>(wa, wc, own, pos0, h1.x, h1.y, h1.z, Zc, Ss, Ws, span, bkey, bpos);
             }
         }
-        // minimum over the G lanes of a middle hit
+        // minimum over the G lanes of a middle hit (keys are unique or ~0)
         for (int m = 1; m < G; m <<= 1) {
-            SeedBest o;
-            o.found = __shfl_xor((int)best.found, m) != 0;
-            o.sc = __shfl_xor(best.sc, m);
-            o.id0 = (uint16_t)__shfl_xor((int)best.id0, m);
-            o.id2 = (uint16_t)__shfl_xor((int)best.id2, m);
-            o.pos0 = __shfl_xor(best.pos0, m);
-            o.pos2 = __shfl_xor(best.pos2, m);
-            if (seed_better(o, best)) best = o;
+            const uint32_t olo = (uint32_t)lane_xor((int)(uint32_t)bkey, m);
+            const uint32_t ohi = (uint32_t)lane_xor((int)(uint32_t)(bkey >> 32), m);
+            const uint32_t opos = (uint32_t)lane_xor((int)bpos, m);
+            const unsigned long long o = ((unsigned long long)ohi << 32) | olo;
+            if (o < bkey) {
+                bkey = o;
+                bpos = opos;
+            }
         }
-        const bool emit = best.found && c == 0 && g < seed_items;
+        const bool emit = bkey != ~0ull && c == 0 && g < seed_items;
         const int r = wave_append(emit, &S.cnt[0]);
         const int l = wave_append(emit, n_nxt);
         if (emit) {
-            const float x0b = wa.x[best.pos0], y0b = wa.y[best.pos0], z0b = wa.z[best.pos0];
-            const float x2b = wc.x[best.pos2], y2b = wc.y[best.pos2], z2b = wc.z[best.pos2];
-            const uint16_t id1 = wb.id[p1];
-            Rec R;
-            const float d12 = z2b - z1;
-            R.xb = x2b; R.yb = y2b; R.zb = z2b;
-            R.tx = (x2b - x1) / d12;
-            R.ty = (y2b - y1) / d12;
-            R.key = id1; R.h0 = best.id0; R.h1 = id1; R.h2 = best.id2; R.last = best.id2;
-            R.len = 3; R.last_t = (uint8_t)t;
-            W.rec[hb + r] = R;
-            // tracklet fit of the seed, hits in traversal order (Section 3,
-            // "Tracklet filter"): chi2 = ((v.x)^2 + (v.y)^2) / (v.v) with
-            // v = (z2-z1, z0-z2, z1-z0) orthogonal to (1,1,1) and to z
-            const float v0 = z2b - z1, v1 = z0b - z2b, v2 = z1 - z0b;
-            const float ssx = ((v0 * x0b) + (v1 * x1)) + (v2 * x2b);
-            const float ssy = ((v0 * y0b) + (v1 * y1)) + (v2 * y2b);
-            const float n2 = ((v0 * v0) + (v1 * v1)) + (v2 * v2);
-            W.rchi2[hb + r] = ((ssx * ssx) + (ssy * ssy)) / n2;
-            nxt.put(l, (uint16_t)r);
-            if (follow_next) {
-                float bsc;
-                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, claim, R, t + 1, bsc);
-                put_result(L, W, hb, nxt.cap, l, r, pb, bsc);
+            if (kLds && l >= CAP) {
+                S.ovf = 1;
+            } else {
+                const int pos0 = (int)(bpos & 0xFFFFu), pos2 = (int)(bpos >> 16);
+                const Hit16 h0 = at(wa.h, pos0);
+                const Hit16 h2 = at(wc.h, pos2);
+                const float x1 = h1.x, y1 = h1.y, z1 = h1.z;
+                Rec R;
+                const float d12 = h2.z - z1;
+                R.xb = h2.x; R.yb = h2.y; R.zb = h2.z;
+                R.tx = (h2.x - x1) / d12;
+                R.ty = (h2.y - y1) / d12;
+                R.key = id_of(h1); R.h0 = id_of(h0); R.h1 = id_of(h1); R.h2 = id_of(h2); R.last = id_of(h2);
+                R.len = 3; R.last_t = (uint8_t)t;
+                at(v.rec(), r) = R;
+                // tracklet fit of the seed, hits in traversal order (Section 3,
+                // "Tracklet filter"): chi2 = ((v.x)^2 + (v.y)^2) / (v.v) with
+                // v = (z2-z1, z0-z2, z1-z0) orthogonal to (1,1,1) and to z
+                const float v0 = h2.z - z1, v1 = h0.z - h2.z, v2 = z1 - h0.z;
+                const float ssx = ((v0 * h0.x) + (v1 * x1)) + (v2 * h2.x);
+                const float ssy = ((v0 * h0.y) + (v1 * y1)) + (v2 * h2.y);
+                const float n2 = ((v0 * v0) + (v1 * v1)) + (v2 * v2);
+                at(v.aux(), r).chi2 = ((ssx * ssx) + (ssy * ssy)) / n2;
+                at(nxt, l) = (uint16_t)r;
+                if (follow_next) {
+                    float bsc;
+                    const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
+                    put_result<kLds, CAP>(v, l, r, pb, bsc);
+                }
             }
         }
     }
@@ -881,29 +1045,32 @@ __device__ void stage_seed_follow(const sbt_params &P, const Work &W, int hb, in
 // append their best hit and flag their claim set.  Tracks that have now missed
 // more than max_consecutive_misses modules in a row become final; the others
 // stay active for the next module.
-template <int B, bool kLds>
-__device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb, int t, Shared<B> &S,
-                                     const Lds &L, uint32_t *own, const AList &act, int n_act, const AList &nxt,
-                                     int *n_nxt)
+template <int B, bool kLds, int CAP>
+__device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, Shared<B> &S, uint32_t *own,
+                                     const uint16_t *act, int n_act, uint16_t *nxt, int *n_nxt)
 {
-    const Win wc = window<B, kLds>(P, L, S, W, hb, t);
-    const unsigned long long *__restrict__ claim = W.claim + hb;
+    const Prm P = fresh(PP);
+    const Ev v = fresh(v0);
+    const Win wc = window<B, kLds, CAP>(P, S, v, t);
+    const unsigned long long *__restrict__ claim = v.claim();
+    uint16_t *fin = v.list(kListFin);
     for (int base = 0; base < n_act; base += B) {
         const int a = base + (int)threadIdx.x;
         bool done = false, keep = false;
         int r = 0;
         if (a < n_act) {
-            r = act.get(a);
-            const bool in_lds = a < act.cap;
-            const uint32_t pb = in_lds ? L.sbest[a] : W.rbest[hb + r];
-            Rec R = W.rec[hb + r];
+            r = at(act, a);
+            uint32_t pb;
+            float bsc;
+            get_result<kLds, CAP>(v, a, r, pb, bsc);
+            Rec R = at(v.rec(), r);
             int last_t = R.last_t;
             if (pb != 0xFFFFFFFFu) {
                 const uint16_t best = (uint16_t)(pb & 0xFFFF);
                 const int bpos = (int)(pb >> 16);
-                const unsigned long long kap = claim_key(in_lds ? L.sbsc[a] : W.rbsc[hb + r], R.key, t);
-                bool win = claim[best] == kap;
-                if (R.len == 3) win = win && claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap;
+                const unsigned long long kap = claim_key(bsc, R.key, t);
+                bool win = at(claim, best) == kap;
+                if (R.len == 3) win = win && at(claim, R.h0) == kap && at(claim, R.h1) == kap && at(claim, R.h2) == kap;
                 if (win) {
                     set_flag(own, best);
                     if (R.len == 3) {
@@ -911,112 +1078,116 @@ __device__ void stage_follow_resolve(const sbt_params &P, const Work &W, int hb,
                         set_flag(own, R.h1);
                         set_flag(own, R.h2);
                     }
-                    W.prev[hb + best] = R.last;
-                    const float xn = wc.x[bpos], yn = wc.y[bpos], zn = wc.z[bpos];
-                    const float dab = zn - R.zb;
-                    R.tx = (xn - R.xb) / dab;
-                    R.ty = (yn - R.yb) / dab;
-                    R.xb = xn; R.yb = yn; R.zb = zn;
+                    at(v.link(), 2u * best) = R.last;
+                    const Hit16 hn = at(wc.h, bpos);
+                    const float dab = hn.z - R.zb;
+                    R.tx = (hn.x - R.xb) / dab;
+                    R.ty = (hn.y - R.yb) / dab;
+                    R.xb = hn.x; R.yb = hn.y; R.zb = hn.z;
                     R.last = best;
                     R.len = (uint8_t)(R.len + 1);
                     R.last_t = (uint8_t)t;
-                    W.rec[hb + r] = R;
+                    at(v.rec(), r) = R;
                     last_t = t;
                 }
             }
-            done = (t - last_t) >= P.max_consecutive_misses + 1;
+            done = (t - last_t) >= P.misses + 1;
             keep = !done;
         }
         const int f = wave_append(done, &S.cnt[3]);
-        if (done) W.fin[hb + f] = (uint16_t)r;
+        if (done) at(fin, f) = (uint16_t)r;
         const int l = wave_append(keep, n_nxt);
-        if (keep) nxt.put(l, (uint16_t)r);
+        if (keep) {
+            if (kLds && l >= CAP) S.ovf = 1;
+            else at(nxt, l) = (uint16_t)r;
+        }
     }
 }
 
-// The owner flags of an event: in LDS when the event fits, else in memory.
-__device__ __forceinline__ uint32_t *owner_words(const Work &W, int e, int hb) { return W.owner + (hb >> 5) + e; }
-
-// whether an event runs the LDS instantiation of the tracking stages
-template <int B>
-__device__ __forceinline__ bool event_in_lds(const Shared<B> &S, const Lds &L, int N)
+// whether an event fits the LDS instantiation of the tracking stages
+template <int B, int CAP>
+__device__ __forceinline__ bool event_fits_lds(const Shared<B> &S, int N, int own_cap)
 {
-    return uni(S.maxmod) <= L.cap && N <= L.own_cap;
-}
-
-template <int B>
-__device__ __forceinline__ uint32_t *owner_ptr(const Shared<B> &S, const Lds &L, const Work &W, int e, int hb, int N)
-{
-    return event_in_lds<B>(S, L, N) ? L.own : owner_words(W, e, hb);
+    return CAP > 0 && uni(S.maxmod) <= CAP && N <= own_cap;
 }
 
 // Seeding and following over all modules.  Leaves the final record list in
-// W.fin and its length in S.cnt[3]; with writeback the owner flags are also
-// copied to memory.
-template <int B, bool kLds>
-__device__ void stage_track_impl(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S,
-                                 const Lds &L, bool writeback)
+// the final list and its length in S.cnt[3]; with writeback the LDS flags are
+// copied to memory.  The LDS instantiation returns false when an active list
+// outgrew its LDS capacity (the event is then run again from memory).
+template <int B, bool kLds, int CAP>
+__device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S, bool writeback)
 {
-    const int M = P.n_modules;
-    uint32_t *own = kLds ? L.own : owner_words(W, e, hb);
+    const Prm P = fresh(PP);
+    const int M = P.M, N = v.N;
+    uint32_t *own = kLds ? Lay<CAP>::own() : v.own();
     const int nw = (N + 31) >> 5;
-    for (int i = threadIdx.x; i < nw; i += B) own[i] = 0u;
+    for (int i = threadIdx.x; i < nw; i += B) at(own, i) = 0u;
     for (int i = threadIdx.x; i < N; i += B) {
-        W.claim[hb + i] = kNoClaim;
-        W.key2rec[hb + i] = kNone;
+        at(v.claim(), i) = kNoClaim;
+        at(v.link(), 2u * i + 1u) = kNone;
     }
     if (threadIdx.x == 0) {
         S.cnt[0] = 0; S.cnt[1] = 0; S.cnt[2] = 0; S.cnt[3] = 0;
+        S.ovf = 0;
     }
     RingStage<B> R;
     if (kLds)
         for (int u = 0; u < 4 && u < M; ++u) {
-            ring_load<B>(P, W, hb, u, S, L, R);
-            ring_store<B>(P, W, hb, u, S, L, R);
+            ring_load<B>(P, v, u, S, R);
+            ring_store<B, CAP>(P, v, u, S, R);
         }
     __syncthreads();
-    const AList l0 = {kLds ? L.al0 : nullptr, W.act0 + hb, kLds ? L.cap : 0};
-    const AList l1 = {kLds ? L.al1 : nullptr, W.act1 + hb, kLds ? L.cap : 0};
+    uint16_t *l0 = kLds ? Lay<CAP>::al(0) : v.list(kListAct0);
+    uint16_t *l1 = kLds ? Lay<CAP>::al(1) : v.list(kListAct1);
     int par = 0;
-    stage_seed_follow<B, kLds>(P, W, hb, 2, S, L, own, l0, &S.cnt[1], 0, M > 3);
+    stage_seed_follow<B, kLds, CAP>(PP, v, 2, S, own, l0, &S.cnt[1], 0, M > 3);
     __syncthreads();
+    if (kLds && uni(S.ovf)) return false;
     for (int t = 3; t < M; ++t) {
         // act (n_act tracks) holds every forming track with its search into
         // t done: resolve t keeping the survivors in nxt, then seed t and
         // search t+1
         const int n_act = uni(S.cnt[1 + par]);
-        const AList &act = par ? l1 : l0;
-        const AList &nxt = par ? l0 : l1;
+        uint16_t *act = par ? l1 : l0;
+        uint16_t *nxt = par ? l0 : l1;
         const bool more = t + 1 < M;
-        if (kLds && more) ring_load<B>(P, W, hb, t + 1, S, L, R);
-        stage_follow_resolve<B, kLds>(P, W, hb, t, S, L, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
-        if (kLds && more) ring_store<B>(P, W, hb, t + 1, S, L, R);
+        if (kLds && more) ring_load<B>(fresh(PP), fresh(v), t + 1, S, R);
+        stage_follow_resolve<B, kLds, CAP>(PP, v, t, S, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
+        if (kLds && more) ring_store<B, CAP>(fresh(PP), fresh(v), t + 1, S, R);
         __syncthreads();
         const int n_keep = uni(S.cnt[1 + (par ^ 1)]);
         if (threadIdx.x == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
-        stage_seed_follow<B, kLds>(P, W, hb, t, S, L, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
+        if (!(kLds && uni(S.ovf)))
+            stage_seed_follow<B, kLds, CAP>(PP, v, t, S, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
         __syncthreads();
+        if (kLds && uni(S.ovf)) return false;
         par ^= 1;
     }
     const int n_act = uni(S.cnt[1 + par]);
     const int nf = uni(S.cnt[3]);
-    const AList &act = par ? l1 : l0;
-    for (int a = threadIdx.x; a < n_act; a += B) W.fin[hb + nf + a] = act.get(a);
-    if (kLds && writeback) {
-        uint32_t *g = owner_words(W, e, hb);
-        for (int i = threadIdx.x; i < nw; i += B) g[i] = own[i];
-    }
+    const uint16_t *act = par ? l1 : l0;
+    uint16_t *fin = v.list(kListFin);
+    for (int a = threadIdx.x; a < n_act; a += B) at(fin, nf + a) = at(act, a);
+    if (kLds && writeback)
+        for (int i = threadIdx.x; i < nw; i += B) at(v.own(), i) = at(own, i);
     __syncthreads();
     if (threadIdx.x == 0) S.cnt[3] = nf + n_act;
     __syncthreads();
+    return true;
 }
 
-template <int B>
-__device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, int N, Shared<B> &S, const Lds &L,
-                            bool writeback)
+// Runs the tracking stages; returns true when the event's flags ended in LDS.
+template <int B, int CAP>
+__device__ bool stage_track(const sbt_params &P, const Ev &v, Shared<B> &S, int own_cap, bool writeback)
 {
-    if (event_in_lds<B>(S, L, N)) stage_track_impl<B, true>(P, W, e, hb, N, S, L, writeback);
-    else stage_track_impl<B, false>(P, W, e, hb, N, S, L, writeback);
+    if constexpr (CAP > 0) {
+        if (event_fits_lds<B, CAP>(S, v.N, own_cap)) {
+            if (stage_track_impl<B, true, CAP>(P, v, S, writeback)) return true;
+        }
+    }
+    stage_track_impl<B, false, CAP>(P, v, S, false);
+    return false;
 }
 
 // ---------------------------------------------------------------- tracklet filter
@@ -1024,74 +1195,80 @@ __device__ void stage_track(const sbt_params &P, const Work &W, int e, int hb, i
 // fit chi2 is under the threshold and none of its hits is flagged; candidates
 // sharing hits keep the one with the minimum (chi2, key).
 template <int B>
-__device__ void stage_filter(const sbt_params &P, const Work &W, int hb, int n_fin, const uint32_t *own)
+__device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, const uint32_t *own)
 {
-    const float X = P.max_tracklet_chi2;
-    unsigned long long *__restrict__ claim = W.claim + hb;
+    const Ev v = fresh(v0);
+    const float X = fresh(PP).X;
+    unsigned long long *__restrict__ claim = v.claim();
+    const uint16_t *fin = v.list(kListFin);
     for (int a = threadIdx.x; a < n_fin; a += B) {
-        const int r = W.fin[hb + a];
-        const Rec R = W.rec[hb + r];
-        uint8_t fl = 0;
+        const int r = at(fin, a);
+        const Rec R = at(v.rec(), r);
+        uint32_t fl = 0;
         if (R.len >= 4) {
             fl = kFlagAccepted;
         } else {
-            const float c2 = W.rchi2[hb + r];
+            const float c2 = at(v.aux(), r).chi2;
             if (c2 < X && is_free(own, R.h0) && is_free(own, R.h1) && is_free(own, R.h2)) {
                 const unsigned long long kap = claim_key(c2, R.key, kFilterStage);
-                atomicMin(&claim[R.h0], kap);
-                atomicMin(&claim[R.h1], kap);
-                atomicMin(&claim[R.h2], kap);
+                atomicMin(&at(claim, R.h0), kap);
+                atomicMin(&at(claim, R.h1), kap);
+                atomicMin(&at(claim, R.h2), kap);
                 fl = kFlagCandidate;
             }
         }
-        W.rflag[hb + r] = fl;
+        at(v.aux(), r).flag = fl;
     }
     __syncthreads();
     for (int a = threadIdx.x; a < n_fin; a += B) {
-        const int r = W.fin[hb + a];
-        uint8_t fl = W.rflag[hb + r];
-        const Rec R = W.rec[hb + r];
+        const int r = at(fin, a);
+        const RecAux x = at(v.aux(), r);
+        uint32_t fl = x.flag;
+        const Rec R = at(v.rec(), r);
         if (fl == kFlagCandidate) {
-            const unsigned long long kap = claim_key(W.rchi2[hb + r], R.key, kFilterStage);
-            fl = (claim[R.h0] == kap && claim[R.h1] == kap && claim[R.h2] == kap) ? kFlagAccepted : 0;
+            const unsigned long long kap = claim_key(x.chi2, R.key, kFilterStage);
+            fl = (at(claim, R.h0) == kap && at(claim, R.h1) == kap && at(claim, R.h2) == kap) ? kFlagAccepted : 0;
         }
-        if (fl == kFlagAccepted) W.key2rec[hb + R.key] = (uint16_t)r;
+        if (fl == kFlagAccepted) at(v.link(), 2u * R.key + 1u) = (uint16_t)r;
     }
     __syncthreads();
 }
 
 // ---------------------------------------------------------------- per-event compaction
 // Accepted tracks in key order: per-event track offsets and hit ids into the
-// staging arrays, counts into ev_nt / ev_nh.
+// staging arrays, counts into the event's counters.
 template <int B>
-__device__ void stage_compact(const Work &W, int e, int hb, int N, int *s_scan)
+__device__ void stage_compact(const Ev &v0, int *s_scan)
 {
+    const Ev v = fresh(v0);
+    const int N = v.N;
     int tcarry = 0, hcarry = 0;
     bool bad = false;
-    for (int base = 0; base < N; base += B) {
+    int phase = 0;
+    for (int base = 0; base < N; base += B, ++phase) {
         const int key = base + (int)threadIdx.x;
-        const uint16_t r = key < N ? W.key2rec[hb + key] : kNone;
+        const uint16_t r = key < N ? at(v.link(), 2u * key + 1u) : kNone;
         Rec R;
-        int packed = 0;
+        int len = 0;
         if (r != kNone) {
-            R = W.rec[hb + r];
-            packed = (1 << 16) | R.len;
+            R = at(v.rec(), r);
+            len = R.len;
         }
         int total;
-        const int ex = block_excl_scan<B>(packed, s_scan, &total);
+        const int ex = block_excl_scan<B>((r != kNone ? (1 << 16) : 0) | len, s_scan, phase, &total);
         if (r != kNone) {
             const int ti = tcarry + (ex >> 16);
             const int hi = hcarry + (ex & 0xFFFF);
             // tracks are disjoint, so hi + len <= N; the checks below only
             // keep a broken invariant from turning into a stray access
             if (hi + R.len <= N) {
-                W.st_toff[hb + ti] = hi;
-                uint16_t *out = W.st_hits + hb + hi;
+                at(v.st_toff(), ti) = hi;
+                uint16_t *out = v.st_hits() + hi;
                 uint16_t p = R.last;
                 for (int j = R.len - 1; j >= 3; --j) {
                     if (p >= N) { bad = true; break; }
                     out[j] = p;
-                    p = W.prev[hb + p];
+                    p = at(v.link(), 2u * p);
                 }
                 out[2] = R.h2;
                 out[1] = R.h1;
@@ -1103,10 +1280,10 @@ __device__ void stage_compact(const Work &W, int e, int hb, int N, int *s_scan)
         tcarry += total >> 16;
         hcarry += total & 0xFFFF;
     }
-    if (bad) W.ev_st[e] = (int)SBT_EV_INTERNAL;
+    if (bad) v.info().st = (int)SBT_EV_INTERNAL;
     if (threadIdx.x == 0) {
-        W.ev_nt[e] = hcarry <= N ? tcarry : 0;
-        W.ev_nh[e] = hcarry <= N ? hcarry : 0;
+        v.info().nt = hcarry <= N ? tcarry : 0;
+        v.info().nh = hcarry <= N ? hcarry : 0;
     }
 }
 

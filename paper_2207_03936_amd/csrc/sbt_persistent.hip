@@ -1,0 +1,71 @@
+// Batched form: a persistent work-stealing kernel that runs every stage of an
+// event inside one workgroup and then takes the next event (largest first)
+// from a device counter.  Built once per workgroup width (SBT_TPE).
+#include <hip/hip_runtime.h>
+
+#include "sbt.h"
+#include "sbt_device.h"
+#include "sbt_kernels.h"
+
+#ifndef SBT_TPE
+#error "SBT_TPE (workgroup width) must be defined"
+#endif
+
+using namespace sbt;
+
+template <int B, int CAP>
+__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W0, int own_cap, int sortcap)
+{
+    __shared__ Shared<B> S;
+    for (;;) {
+        // the workspace base is hidden from the optimiser per event, so the
+        // pointers derived from it are not hoisted out of this loop
+        Work W = W0;
+        W.base = opq(W0.base);
+        W.H = opq(W0.H);
+        W.E = opq(W0.E);
+        if (threadIdx.x == 0) {
+            const int idx = (int)atomicAdd(ws_counterp(W), 1u);
+            S.e = idx < H.n_events ? ws_orderp(W)[idx] : -1;
+        }
+        __syncthreads();
+        const int e = uni(S.e);
+        if (e < 0) break;
+        int hb, N;
+        const int st = load_event<B>(P, H, e, S, &hb, &N);
+        if (threadIdx.x == 0) ws_evinfo(W)[e].st = st;
+        if (st == 0) {
+            const Ev v = event_view(W, e, hb, N);
+            stage_sort<B>(P, H, v, S, sortcap);
+            const bool in_lds = stage_track<B, CAP>(P, v, S, own_cap, false);
+            const int n_fin = uni(S.cnt[3]);
+            if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own());
+            else stage_filter<B>(P, v, n_fin, v.own());
+            stage_compact<B>(v, S.scan);
+        } else if (threadIdx.x == 0) {
+            ws_evinfo(W)[e].nt = 0;
+            ws_evinfo(W)[e].nh = 0;
+        }
+        __syncthreads();
+    }
+}
+
+#define SBT_CAT2(a, b) a##b
+#define SBT_CAT(a, b) SBT_CAT2(a, b)
+
+namespace sbt {
+
+const void *SBT_CAT(persistent_kernel_, SBT_TPE)(int cap)
+{
+    switch (cap) {
+    case 0: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 0>);
+    case 256: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 256>);
+    case 448: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 448>);
+    case 672: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 672>);
+    case 1024: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 1024>);
+    case 1536: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 1536>);
+    default: return nullptr;
+    }
+}
+
+}  // namespace sbt
