@@ -377,6 +377,7 @@ __device__ __forceinline__ int lane_xor(int v, int m)
 //   frank  unflagged positions before each doublet-module position
 //   al0/1  active-track lists (CAP entries; more sends the event to memory)
 //   res    per active slot: best hit id | window position << 16, scatter
+//   cfree  unflagged-position bits of the seeding stage's third module
 //   own    hit-flag bitmap of the event when N <= own_cap
 extern __shared__ __align__(16) char g_lds[];
 
@@ -389,7 +390,8 @@ __host__ __device__ constexpr uint32_t lay_frank(int cap) { return lay_freem(cap
 __host__ __device__ constexpr uint32_t lay_al0(int cap) { return lay_frank(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_al1(int cap) { return lay_al0(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_res(int cap) { return lay_al1(cap) + a16(2u * cap); }
-__host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_res(cap) + 8u * cap; }
+__host__ __device__ constexpr uint32_t lay_cfree(int cap) { return lay_res(cap) + 8u * cap; }
+__host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_cfree(cap) + a16(8u * (uint32_t)((cap + 63) / 64)); }
 
 // sort bins: 1024 in total, a power of two per module
 constexpr int kSortBins = 1024;
@@ -432,6 +434,10 @@ struct Lay {
         return reinterpret_cast<unsigned long long *>(g_lds + lay_res(CAP));
     }
     static __device__ __forceinline__ uint32_t *own() { return reinterpret_cast<uint32_t *>(g_lds + lay_own(CAP)); }
+    static __device__ __forceinline__ unsigned long long *cfree()
+    {
+        return reinterpret_cast<unsigned long long *>(g_lds + lay_cfree(CAP));
+    }
 };
 
 // static LDS shared by the stages of one event
@@ -669,17 +675,14 @@ struct RingStage {
     uint16_t qp[PF];
 };
 
-// coarse-index entries owned by position i of an n-hit slot whose phi16 is
-// q (qp: phi16 of position i-1): every high byte b with
-// high(qp) < b <= high(q) starts at i; the last position also closes the
-// table with n
-__device__ __forceinline__ void tab_fill(uint16_t *tab, int i, int n, uint16_t q, uint16_t qp)
+// coarse-index entries owned by position i > 0 of a slot whose phi16 is q
+// (qp: phi16 of position i-1): every high byte b with high(qp) < b <=
+// high(q) starts at i.  The entries up to the first hit's high byte (0) and
+// above the last hit's (n) are written by all lanes together.
+__device__ __forceinline__ void tab_fill(uint16_t *tab, int i, uint16_t q, uint16_t qp)
 {
-    const int b_lo = i == 0 ? 0 : (qp >> 8) + 1;
-    const int b_hi = q >> 8;
-    for (int b = b_lo; b <= b_hi; ++b) tab[b] = (uint16_t)i;
-    if (i == n - 1)
-        for (int b = b_hi + 1; b < kTab; ++b) tab[b] = (uint16_t)n;
+    if (i == 0) return;
+    for (int b = (qp >> 8) + 1; b <= (q >> 8); ++b) tab[b] = (uint16_t)i;
 }
 
 template <int B>
@@ -709,21 +712,29 @@ __device__ __forceinline__ void ring_store(const Prm &P, const Ev &v, int u, Sha
     if (threadIdx.x == 0) S.slot_n[s] = n;
     Hit16 *ring = Lay<CAP>::ring(s);
     uint16_t *tab = Lay<CAP>::tab(s);
-    if (n == 0)
-        for (int b = threadIdx.x; b < kTab; b += B) tab[b] = 0;
+    const Hit16 *src = v.hs() + g;
+    // n == 0: every entry is 0
+    int hi_first = kTab, hi_last = kTab;
+    if (n > 0) {
+        hi_first = uni(q_of(at(src, 0)) >> 8);
+        hi_last = uni(q_of(at(src, n - 1)) >> 8);
+    }
+    for (int b = threadIdx.x; b < kTab; b += B) {
+        if (b <= hi_first) tab[b] = 0;
+        else if (b > hi_last) tab[b] = (uint16_t)n;
+    }
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
             ring[i] = R.h[j];
-            tab_fill(tab, i, n, q_of(R.h[j]), R.qp[j]);
+            tab_fill(tab, i, q_of(R.h[j]), R.qp[j]);
         }
     }
-    const Hit16 *src = v.hs() + g;
     for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {
         const Hit16 h = at(src, i);
         ring[i] = h;
-        tab_fill(tab, i, n, q_of(h), q_of(at(src, i - 1)));
+        tab_fill(tab, i, q_of(h), q_of(at(src, i - 1)));
     }
 }
 
@@ -763,17 +774,71 @@ __device__ __forceinline__ int pendulum_pick(const uint16_t *F, int nf, int j, i
     return pos;
 }
 
+// The same picks for K = 4 with the four partner ranks of a middle hit on
+// the four lanes of a quad (c = lane & 3): lane c loads the c-th unflagged
+// position upwards from s0 and the c-th downwards below it and turns them
+// into visit ranks; the quad exchanges the eight ranks, every lane merges
+// the two ascending lists and keeps the c-th smallest, whose rank gives its
+// position back (rank 2o: s0 + o, rank 2o - 1: s0 - o).  All four lanes of
+// the quad must be active.
+template <int CTRL>
+__device__ __forceinline__ int quad_bcast(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ int pendulum_quad(const uint16_t *F, int nf, int j, int s0, int na, int hu, int hd, int c)
+{
+    constexpr int kInf = 0x7fffffff;
+    int ru = kInf, rd = kInf;
+    if (c < nf) {
+        int iu = j + c;
+        if (iu >= nf) iu -= nf;
+        int id = j - 1 - c;
+        if (id < 0) id += nf;
+        const int pu = at(F, iu), pd = at(F, id);
+        int o = pu - s0;
+        if (o < 0) o += na;
+        if (o <= hu) ru = 2 * o;
+        int od = s0 - pd;
+        if (od < 0) od += na;
+        if (od >= 1 && od <= hd) rd = 2 * od - 1;
+    }
+    int u0 = quad_bcast<0x00>(ru), u1 = quad_bcast<0x55>(ru), u2 = quad_bcast<0xAA>(ru), u3 = quad_bcast<0xFF>(ru);
+    int d0 = quad_bcast<0x00>(rd), d1 = quad_bcast<0x55>(rd), d2 = quad_bcast<0xAA>(rd), d3 = quad_bcast<0xFF>(rd);
+    int pick = kInf;
+#pragma unroll
+    for (int step = 0; step < 4; ++step) {
+        const bool up = u0 < d0;
+        const int take = up ? u0 : d0;
+        if (step == c) pick = take;
+        if (up) { u0 = u1; u1 = u2; u2 = u3; u3 = kInf; }
+        else { d0 = d1; d1 = d2; d2 = d3; d3 = kInf; }
+    }
+    if (pick == kInf) return -1;
+    int pos;
+    if ((pick & 1) == 0) {
+        pos = s0 + (pick >> 1);
+        if (pos >= na) pos -= na;
+    } else {
+        pos = s0 - ((pick + 1) >> 1);
+        if (pos < 0) pos += na;
+    }
+    return pos;
+}
+
 // Best third hit for one doublet: the key orders like the comparison
 // (found, scatter, id0, id2) -- scatter bits << 32 | id0 << 16 | id2, ~0 when
 // nothing was found (scatters are >= +0, so their bits order like the
 // values); pos holds the window positions pos0 | pos2 << 16.
 template <bool kLds>
-__device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const uint32_t *own, int pos0, float x1,
-                                             float y1, float z1, float Zc, float Ss, uint16_t Ws, uint16_t span,
-                                             unsigned long long &bkey, uint32_t &bpos)
+__device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const uint32_t *own,
+                                             const unsigned long long *cfree, int pos0, float x1, float y1, float z1,
+                                             float Zc, float Ss, uint16_t Ws, uint16_t span, unsigned long long &bkey,
+                                             uint32_t &bpos)
 {
     const Hit16 h0 = at(wa.h, pos0);
-    const uint16_t id0 = id_of(h0);
+    const uint32_t id0 = id_of(h0);
     const float d01 = z1 - h0.z;
     const float tx = (x1 - h0.x) / d01;
     const float ty = (y1 - h0.y) / d01;
@@ -782,26 +847,24 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
     const int nc = wc.n;
     if (nc == 0) return;
     const uint16_t lo = (uint16_t)(qe - Ws);
-    int st = win_lower_bound<kLds>(wc, lo);
-    if (st == nc) st = 0;
+    int pc = win_lower_bound<kLds>(wc, lo);
+    if (pc == nc) pc = 0;
     for (int jj = 0; jj < nc; ++jj) {
-        int pc = st + jj;
-        if (pc >= nc) pc -= nc;
+        // LDS: the flag bit is addressed by position, so it loads alongside the hit
+        const bool fpos = kLds ? ((at(cfree, (uint32_t)pc >> 6) >> (pc & 63)) & 1ull) != 0ull : true;
         const Hit16 h2 = at(wc.h, pc);
         if ((uint16_t)(q_of(h2) - lo) > span) break;
-        const uint16_t id2 = id_of(h2);
-        if (!is_free(own, id2)) continue;
+        const uint32_t id2 = id_of(h2);
+        const bool fr = kLds ? fpos : is_free(own, id2);
         const float dz = h2.z - z1;
         const float dx = (x1 + tx * dz) - h2.x;
         const float dy = (y1 + ty * dz) - h2.y;
         const float sc = (dx * dx) + (dy * dy);
-        if (!(sc < Ss)) continue;
-        const unsigned long long k =
-            ((unsigned long long)__float_as_uint(sc) << 32) | ((uint32_t)id0 << 16) | id2;
-        if (k < bkey) {
-            bkey = k;
-            bpos = (uint32_t)pos0 | ((uint32_t)pc << 16);
-        }
+        const unsigned long long k = ((unsigned long long)__float_as_uint(sc) << 32) | (id0 << 16) | id2;
+        const bool better = fr && (sc < Ss) && (k < bkey);
+        bkey = better ? k : bkey;
+        bpos = better ? ((uint32_t)pos0 | ((uint32_t)pc << 16)) : bpos;
+        pc = pc + 1 == nc ? 0 : pc + 1;
     }
 }
 
@@ -829,25 +892,29 @@ __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, flo
         const float dzc = Zc - R.zb;
         const uint16_t qe = phi16(R.xb + R.tx * dzc, R.yb + R.ty * dzc);
         const uint16_t lo = (uint16_t)(qe - Wf);
-        int st = win_lower_bound<kLds>(wc, lo);
-        if (st == nc) st = 0;
+        int pc = win_lower_bound<kLds>(wc, lo);
+        if (pc == nc) pc = 0;
+        // No hit of module u is flagged yet: flags are set only when a
+        // module is resolved, and u is resolved after this search.  The
+        // flag test of the method is therefore always passed here.
+        // (scatter, id) packed so that one comparison orders both
+        unsigned long long bk = ~0ull;
         for (int j = 0; j < nc; ++j) {
-            int pc = st + j;
-            if (pc >= nc) pc -= nc;
             const Hit16 h = at(wc.h, pc);
             if ((uint16_t)(q_of(h) - lo) > span) break;
-            const uint16_t id = id_of(h);
-            if (!is_free(own, id)) continue;
             const float dz = h.z - R.zb;
             const float dx = (R.xb + R.tx * dz) - h.x;
             const float dy = (R.yb + R.ty * dz) - h.y;
             const float sc = (dx * dx) + (dy * dy);
-            if (!(sc < Sf)) continue;
-            if (best == kNone || sc < bsc || (sc == bsc && id < best)) {
-                best = id;
-                bpos = pc;
-                bsc = sc;
-            }
+            const unsigned long long k = ((unsigned long long)__float_as_uint(sc) << 32) | id_of(h);
+            const bool better = (sc < Sf) && (k < bk);
+            bk = better ? k : bk;
+            bpos = better ? pc : bpos;
+            pc = pc + 1 == nc ? 0 : pc + 1;
+        }
+        if (bk != ~0ull) {
+            best = (uint16_t)(bk & 0xFFFFu);
+            bsc = __uint_as_float((uint32_t)(bk >> 32));
         }
         if (best != kNone) {
             const unsigned long long kap = claim_key(bsc, R.key, u);
@@ -935,12 +1002,18 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
         FM = v.list(kListFreeM) + gb;
     }
     int nf = 0, nfm = 0;
-    const int nmax = na > nbm ? na : nbm;
+    int nmax = na > nbm ? na : nbm;
+    if (kLds && wc.n > nmax) nmax = wc.n;
+    unsigned long long *cfree = kLds ? Lay<CAP>::cfree() : nullptr;
     int phase = 0;
     for (int base = 0; base < nmax; base += B, ++phase) {
         const int p = base + (int)threadIdx.x;
         const bool fa = p < na && is_free(own, win_id(wa, p));
         const bool fb = p < nbm && is_free(own, win_id(wb, p));
+        if (kLds) {
+            const unsigned long long m = __ballot(p < wc.n && is_free(own, win_id(wc, p)));
+            if ((threadIdx.x & 63) == 0 && p < wc.n) at(cfree, (uint32_t)p >> 6) = m;
+        }
         int total;
         const int idx = block_count2<B>(fa, fb, S.scan, phase, &total);
         if (p < na) at(FR, p) = (uint16_t)(nf + (idx & 0xFFFF));
@@ -974,6 +1047,8 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
             }
             continue;
         }
+        // the seeding waves carry the longest dependency chain of the step
+        __builtin_amdgcn_s_setprio(2);
         const int i = g / G, c = g - i * G;
         unsigned long long bkey = ~0ull;
         uint32_t bpos = 0;
@@ -986,10 +1061,16 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
             int s0 = win_lower_bound<kLds>(wa, q_of(h1));
             if (s0 == na) s0 = 0;
             const int j = at(FR, s0);   // first unflagged position >= s0, as an index into F
-            for (int cc = 0; cc < per_lane; ++cc) {
-                const int pos0 = pendulum_pick(F, nf, j, s0, na, hu, hd, c + cc);
-                if (pos0 < 0) break;
-                seed_doublet<kLds>(wa, wc, own, pos0, h1.x, h1.y, h1.z, Zc, Ss, Ws, span, bkey, bpos);
+            if (G == 4) {
+                const int pos0 = pendulum_quad(F, nf, j, s0, na, hu, hd, c);
+                if (pos0 >= 0)
+                    seed_doublet<kLds>(wa, wc, own, cfree, pos0, h1.x, h1.y, h1.z, Zc, Ss, Ws, span, bkey, bpos);
+            } else {
+                for (int cc = 0; cc < per_lane; ++cc) {
+                    const int pos0 = pendulum_pick(F, nf, j, s0, na, hu, hd, c + cc);
+                    if (pos0 < 0) break;
+                    seed_doublet<kLds>(wa, wc, own, cfree, pos0, h1.x, h1.y, h1.z, Zc, Ss, Ws, span, bkey, bpos);
+                }
             }
         }
         // minimum over the G lanes of a middle hit (keys are unique or ~0)
@@ -1038,6 +1119,7 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
     }
 }
 

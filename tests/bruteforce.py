@@ -25,6 +25,10 @@ import oracle
 
 F = np.float32
 FREE = None
+# times the following search met a flagged hit in the module it searches
+# (never, by the step order: a module's hits are flagged only when that
+# module is resolved, after its search)
+FLAGGED_FOLLOW_CANDIDATES = [0]
 
 
 def _circ(a, b):
@@ -101,7 +105,10 @@ def reconstruct_event(x, y, z, mo, module_z, *, reverse=1, K=4, Ws=416, Wf=416,
             qe = phi_of(F(x[hb] + F(tx * dzc)), F(y[hb] + F(ty * dzc)))
             options = []
             for h in members[C]:
-                if owner[h] is not FREE or _circ(q[h], qe) > Wf:
+                if owner[h] is not FREE:
+                    FLAGGED_FOLLOW_CANDIDATES[0] += 1
+                    continue
+                if _circ(q[h], qe) > Wf:
                     continue
                 dz = F(z[h] - z[hb])
                 dx = F(F(x[hb] + F(tx * dz)) - x[h])

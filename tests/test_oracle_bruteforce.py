@@ -139,3 +139,22 @@ def test_thresholds_are_strict():
     base = dict(oracle.DEFAULTS, max_scatter_seeding=1.0)
     assert _run_both(ev, dict(base, max_tracklet_chi2=float(chi2)))[0] == []
     assert _run_both(ev, dict(base, max_tracklet_chi2=up(chi2)))[0] == [(2, 1, 0)]
+
+
+def test_following_never_meets_a_flagged_hit():
+    """The following search into a module never finds a flagged hit there:
+    hits are flagged only when their module is resolved, which comes after
+    its search (the step order of Section 3).  The HIP path relies on this
+    to skip the flag test in its following search."""
+    import bruteforce
+    rng = np.random.default_rng(77)
+    bruteforce.FLAGGED_FOLLOW_CANDIDATES[0] = 0
+    n_tracks = 0
+    for _ in range(60):
+        ev = tiny_random_event(rng)
+        p = _params(rng)
+        got, want = _run_both(ev, p)
+        assert got == want
+        n_tracks += len(want)
+    assert n_tracks > 50
+    assert bruteforce.FLAGGED_FOLLOW_CANDIDATES[0] == 0
