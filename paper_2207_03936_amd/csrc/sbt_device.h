@@ -277,6 +277,21 @@ __device__ __forceinline__ int wave_append(bool pred, int *counter)
     return pred ? base + lane_rank(m) : -1;
 }
 
+// Two appends at once (their atomics overlap); every lane must call it.
+__device__ __forceinline__ void wave_append2(bool p0, int *c0, bool p1, int *c1, int &r0, int &r1)
+{
+    const unsigned long long m0 = __ballot(p0), m1 = __ballot(p1);
+    int b0 = 0, b1 = 0;
+    if (lane_rank(__builtin_amdgcn_read_exec()) == 0) {
+        if (m0) b0 = atomicAdd(c0, __popcll(m0));
+        if (m1) b1 = atomicAdd(c1, __popcll(m1));
+    }
+    b0 = __builtin_amdgcn_readfirstlane(b0);
+    b1 = __builtin_amdgcn_readfirstlane(b1);
+    r0 = p0 ? b0 + lane_rank(m0) : -1;
+    r1 = p1 ? b1 + lane_rank(m1) : -1;
+}
+
 // inclusive prefix sum over the wave: row shifts, then the row broadcasts
 __device__ __forceinline__ int wave_incl_scan(int v)
 {
@@ -376,7 +391,8 @@ __device__ __forceinline__ int lane_xor(int v, int m)
 //   freem  unflagged positions of the middle module
 //   frank  unflagged positions before each doublet-module position
 //   al0/1  active-track lists (CAP entries; more sends the event to memory)
-//   res    per active slot: best hit id | window position << 16, scatter
+//   res    per active slot: the search result (best hit id | window position
+//          << 16, scatter) and the claim set's inputs (key, seed hits)
 //   cfree  unflagged-position bits of the seeding stage's third module
 //   own    hit-flag bitmap of the event when N <= own_cap
 extern __shared__ __align__(16) char g_lds[];
@@ -390,7 +406,7 @@ __host__ __device__ constexpr uint32_t lay_frank(int cap) { return lay_freem(cap
 __host__ __device__ constexpr uint32_t lay_al0(int cap) { return lay_frank(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_al1(int cap) { return lay_al0(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_res(int cap) { return lay_al1(cap) + a16(2u * cap); }
-__host__ __device__ constexpr uint32_t lay_cfree(int cap) { return lay_res(cap) + 8u * cap; }
+__host__ __device__ constexpr uint32_t lay_cfree(int cap) { return lay_res(cap) + 16u * cap; }
 __host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_cfree(cap) + a16(8u * (uint32_t)((cap + 63) / 64)); }
 
 // sort bins: 1024 in total, a power of two per module
@@ -429,10 +445,7 @@ struct Lay {
     {
         return reinterpret_cast<uint16_t *>(g_lds + (i ? lay_al1(CAP) : lay_al0(CAP)));
     }
-    static __device__ __forceinline__ unsigned long long *res()
-    {
-        return reinterpret_cast<unsigned long long *>(g_lds + lay_res(CAP));
-    }
+    static __device__ __forceinline__ uint4 *res() { return reinterpret_cast<uint4 *>(g_lds + lay_res(CAP)); }
     static __device__ __forceinline__ uint32_t *own() { return reinterpret_cast<uint32_t *>(g_lds + lay_own(CAP)); }
     static __device__ __forceinline__ unsigned long long *cfree()
     {
@@ -673,6 +686,7 @@ struct RingStage {
     static constexpr int PF = (512 + B - 1) / B;
     Hit16 h[PF];
     uint16_t qp[PF];
+    int hi_first, hi_last;   // high bytes of the first and last phi16 (kTab when empty)
 };
 
 // coarse-index entries owned by position i > 0 of a slot whose phi16 is q
@@ -692,6 +706,12 @@ __device__ __forceinline__ void ring_load(const Prm &P, const Ev &v, int u, cons
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
     const Hit16 *src = v.hs() + g;
+    R.hi_first = kTab;
+    R.hi_last = kTab;
+    if (n > 0) {
+        R.hi_first = q_of(at(src, 0)) >> 8;
+        R.hi_last = q_of(at(src, n - 1)) >> 8;
+    }
 #pragma unroll
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
@@ -714,11 +734,7 @@ __device__ __forceinline__ void ring_store(const Prm &P, const Ev &v, int u, Sha
     uint16_t *tab = Lay<CAP>::tab(s);
     const Hit16 *src = v.hs() + g;
     // n == 0: every entry is 0
-    int hi_first = kTab, hi_last = kTab;
-    if (n > 0) {
-        hi_first = uni(q_of(at(src, 0)) >> 8);
-        hi_last = uni(q_of(at(src, n - 1)) >> 8);
-    }
+    const int hi_first = uni(R.hi_first), hi_last = uni(R.hi_last);
     for (int b = threadIdx.x; b < kTab; b += B) {
         if (b <= hi_first) tab[b] = 0;
         else if (b > hi_last) tab[b] = (uint16_t)n;
@@ -930,31 +946,25 @@ __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, flo
     return best == kNone ? 0xFFFFFFFFu : ((uint32_t)bpos << 16) | best;
 }
 
-// search result of active slot a (record r): LDS slot in the LDS
-// instantiation, the record's auxiliary data in the memory one
+// Search result of active slot a (record r).  LDS instantiation: the slot's
+// 16 bytes hold the result and what the resolution needs to test the claims
+// without the record: {best | position << 16, scatter, key | h0 << 16,
+// h1 | h2 << 16}, seed hits only for a bare seed (h0 = none otherwise).
+// Memory instantiation: the record's auxiliary data.
 template <bool kLds, int CAP>
-__device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t pb, float bsc)
+__device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t pb, float bsc, const Rec &R)
 {
     if (kLds) {
-        Lay<CAP>::res()[a] = (unsigned long long)pb | ((unsigned long long)__float_as_uint(bsc) << 32);
+        uint4 w;
+        w.x = pb;
+        w.y = __float_as_uint(bsc);
+        w.z = (uint32_t)R.key | ((uint32_t)(R.len == 3 ? R.h0 : kNone) << 16);
+        w.w = (uint32_t)R.h1 | ((uint32_t)R.h2 << 16);
+        Lay<CAP>::res()[a] = w;
     } else {
         RecAux &x = at(v.aux(), r);
         x.best = pb;
         x.bsc = bsc;
-    }
-}
-
-template <bool kLds, int CAP>
-__device__ __forceinline__ void get_result(const Ev &v, int a, int r, uint32_t &pb, float &bsc)
-{
-    if (kLds) {
-        const unsigned long long w = Lay<CAP>::res()[a];
-        pb = (uint32_t)w;
-        bsc = __uint_as_float((uint32_t)(w >> 32));
-    } else {
-        const RecAux &x = at(v.aux(), r);
-        pb = x.best;
-        bsc = x.bsc;
     }
 }
 
@@ -1043,7 +1053,7 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
                 const Rec R = at(v.rec(), r);
                 float bsc;
                 const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
-                put_result<kLds, CAP>(v, a, r, pb, bsc);
+                put_result<kLds, CAP>(v, a, r, pb, bsc, R);
             }
             continue;
         }
@@ -1085,8 +1095,8 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
             }
         }
         const bool emit = bkey != ~0ull && c == 0 && g < seed_items;
-        const int r = wave_append(emit, &S.cnt[0]);
-        const int l = wave_append(emit, n_nxt);
+        int r, l;
+        wave_append2(emit, &S.cnt[0], emit, n_nxt, r, l);
         if (emit) {
             if (kLds && l >= CAP) {
                 S.ovf = 1;
@@ -1115,7 +1125,7 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
                 if (follow_next) {
                     float bsc;
                     const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
-                    put_result<kLds, CAP>(v, l, r, pb, bsc);
+                    put_result<kLds, CAP>(v, l, r, pb, bsc, R);
                 }
             }
         }
@@ -1142,43 +1152,62 @@ __device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, 
         int r = 0;
         if (a < n_act) {
             r = at(act, a);
-            uint32_t pb;
+            uint32_t pb, k0 = 0, k12 = 0;
             float bsc;
-            get_result<kLds, CAP>(v, a, r, pb, bsc);
+            if (kLds) {
+                const uint4 w = Lay<CAP>::res()[a];
+                pb = w.x;
+                bsc = __uint_as_float(w.y);
+                k0 = w.z;
+                k12 = w.w;
+            } else {
+                const RecAux &x = at(v.aux(), r);
+                pb = x.best;
+                bsc = x.bsc;
+            }
             Rec R = at(v.rec(), r);
-            int last_t = R.last_t;
+            if (!kLds) {
+                k0 = (uint32_t)R.key | ((uint32_t)(R.len == 3 ? R.h0 : kNone) << 16);
+                k12 = (uint32_t)R.h1 | ((uint32_t)R.h2 << 16);
+            }
+            bool win = false;
             if (pb != 0xFFFFFFFFu) {
                 const uint16_t best = (uint16_t)(pb & 0xFFFF);
+                const unsigned long long kap = claim_key(bsc, (uint16_t)(k0 & 0xFFFFu), t);
+                const uint16_t h0 = (uint16_t)(k0 >> 16);
+                win = at(claim, best) == kap;
+                if (h0 != kNone)
+                    win = win && at(claim, h0) == kap && at(claim, (uint16_t)(k12 & 0xFFFFu)) == kap &&
+                          at(claim, (uint16_t)(k12 >> 16)) == kap;
+            }
+            int last_t = R.last_t;
+            if (win) {
+                const uint16_t best = (uint16_t)(pb & 0xFFFF);
                 const int bpos = (int)(pb >> 16);
-                const unsigned long long kap = claim_key(bsc, R.key, t);
-                bool win = at(claim, best) == kap;
-                if (R.len == 3) win = win && at(claim, R.h0) == kap && at(claim, R.h1) == kap && at(claim, R.h2) == kap;
-                if (win) {
-                    set_flag(own, best);
-                    if (R.len == 3) {
-                        set_flag(own, R.h0);
-                        set_flag(own, R.h1);
-                        set_flag(own, R.h2);
-                    }
-                    at(v.link(), 2u * best) = R.last;
-                    const Hit16 hn = at(wc.h, bpos);
-                    const float dab = hn.z - R.zb;
-                    R.tx = (hn.x - R.xb) / dab;
-                    R.ty = (hn.y - R.yb) / dab;
-                    R.xb = hn.x; R.yb = hn.y; R.zb = hn.z;
-                    R.last = best;
-                    R.len = (uint8_t)(R.len + 1);
-                    R.last_t = (uint8_t)t;
-                    at(v.rec(), r) = R;
-                    last_t = t;
+                set_flag(own, best);
+                if (R.len == 3) {
+                    set_flag(own, R.h0);
+                    set_flag(own, R.h1);
+                    set_flag(own, R.h2);
                 }
+                at(v.link(), 2u * best) = R.last;
+                const Hit16 hn = at(wc.h, bpos);
+                const float dab = hn.z - R.zb;
+                R.tx = (hn.x - R.xb) / dab;
+                R.ty = (hn.y - R.yb) / dab;
+                R.xb = hn.x; R.yb = hn.y; R.zb = hn.z;
+                R.last = best;
+                R.len = (uint8_t)(R.len + 1);
+                R.last_t = (uint8_t)t;
+                at(v.rec(), r) = R;
+                last_t = t;
             }
             done = (t - last_t) >= P.misses + 1;
             keep = !done;
         }
-        const int f = wave_append(done, &S.cnt[3]);
+        int f, l;
+        wave_append2(done, &S.cnt[3], keep, n_nxt, f, l);
         if (done) at(fin, f) = (uint16_t)r;
-        const int l = wave_append(keep, n_nxt);
         if (keep) {
             if (kLds && l >= CAP) S.ovf = 1;
             else at(nxt, l) = (uint16_t)r;
