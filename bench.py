@@ -71,6 +71,117 @@ def measured_traffic(per_launch_hits: int):
     return d.get("hbm_bytes_per_launch")
 
 
+def measured_sq(per_launch_hits: int):
+    """Instruction counts of the dominant kernel from the committed SQ counter
+    summary, if taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_persistent_mu7.6_x1000_sq.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n_hits") != per_launch_hits:
+        return None
+    return d
+
+
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Device-to-device copy bandwidth measured on this GPU (bytes read plus
+    bytes written per second, GB/s)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2 * 4 * n / sec / 1e9
+
+
+def end_to_end(torch, sbt, ctx, batch, steps):
+    """Whole-batch rate with the hits in pinned host memory at the start and
+    the tracks back in pinned host memory at the end (H2D, reconstruction and
+    D2H on one stream)."""
+    def pinned(a, dt):
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
+        return t
+    hx, hy, hz = pinned(batch.x, np.float32), pinned(batch.y, np.float32), pinned(batch.z, np.float32)
+    heo, hmo = pinned(batch.event_offsets, np.int32), pinned(batch.module_offsets, np.int32)
+    dev = sbt.DeviceBatch(batch)
+    out = sbt.DeviceTracks(batch.n_events, batch.n_hits)
+    ctx.reconstruct(dev, out)
+    torch.cuda.synchronize()
+    T = int(out.eto[-1].item())
+    A = int(out.tho[T].item())
+    oeto = torch.empty(batch.n_events + 1, dtype=torch.int32).pin_memory()
+    otho = torch.empty(T + 1, dtype=torch.int32).pin_memory()
+    oth = torch.empty(max(A, 1), dtype=torch.int32).pin_memory()
+
+    def step():
+        for d, h in ((dev.x, hx), (dev.y, hy), (dev.z, hz), (dev.eo, heo), (dev.mo, hmo)):
+            d.copy_(h, non_blocking=True)
+        ctx.reconstruct(dev, out)
+        oeto.copy_(out.eto, non_blocking=True)
+        otho.copy_(out.tho[:T + 1], non_blocking=True)
+        oth[:A].copy_(out.th[:A], non_blocking=True)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    in_bytes = 12 * batch.n_hits + 4 * (batch.n_events + 1) + 4 * batch.module_offsets.shape[0]
+    out_bytes = 4 * (batch.n_events + 1) + 4 * (T + 1) + 4 * A
+    return dict(events_per_s=round(batch.n_events / sec, 1), ms_per_step=round(sec * 1e3, 4),
+                pcie_bytes_per_step=int(in_bytes + out_bytes),
+                note="hits in pinned host memory before, tracks in pinned host memory after")
+
+
+def _oracle_slice(args):
+    lo, hi, target_s = args
+    import oracle
+    from paper_2207_03936_amd import synth
+    b = _PAR_BATCH.select(range(lo, hi))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.reconstruct(b)
+        n += hi - lo
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            return n, dt
+
+
+def cpu_parallel_baseline(batch, workload, procs, target_s=6.0):
+    """The oracle as it stands, as `procs` independent single-threaded
+    processes on disjoint contiguous slices of the batch, each repeating its
+    slice for about target_s; aggregate = events done / slowest wall time.
+    Runs before the GPU is initialised (fork)."""
+    import multiprocessing as mp
+    global _PAR_BATCH
+    _PAR_BATCH = batch
+    E = batch.n_events
+    procs = max(1, min(procs, E))
+    bounds = [(E * i // procs, E * (i + 1) // procs, target_s) for i in range(procs)]
+    with mp.get_context("fork").Pool(procs) as pool:
+        res = pool.map(_oracle_slice, bounds)
+    n = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    return dict(value=round(n / wall, 2), unit="events/s", cores=procs, kind="oracle",
+                sample=f"{workload} batch split into {procs} contiguous slices, one single-threaded process each, "
+                       f"each slice repeated for about {target_s:.0f} s")
+
+
+_PAR_BATCH = None
+
+
 def serving_leg(params, seconds, fraction=0.5):
     """Continuous-batching server fed by Poisson arrivals of events from the
     mu ~ U{1..25} serving mixture: saturated throughput first, then latency
@@ -134,12 +245,18 @@ def main():
               "several GPUs would each run this same per-GPU path on their own events.", file=sys.stderr)
         sys.exit(2)
 
+    from paper_2207_03936_amd import synth
+    batch = synth.make_batch(args.workload, args.events or None)
+    cpu_par = None
+    if not args.no_cpu:
+        # before the GPU is touched: the processes are forked
+        cpu_par = cpu_parallel_baseline(batch, args.workload, min(16, os.cpu_count() or 1))
+
     import torch
-    from paper_2207_03936_amd import sbt, synth
+    from paper_2207_03936_amd import sbt
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    batch = synth.make_batch(args.workload, args.events or None)
     E, H = batch.n_events, batch.n_hits
     params = sbt.make_params(batch.module_z)
     dev = sbt.DeviceBatch(batch)
@@ -186,6 +303,9 @@ def main():
     alg = algorithmic_bytes(batch, got[0], got[1])
     achieved = alg / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic(H)
+    copy_gbps = copy_bandwidth(torch)
+    sq = measured_sq(H)
+    e2e = end_to_end(torch, sbt, ctx, batch, max(5, min(args.steps, 20)))
 
     result = {
         "metric": "events/s on 1 MI355X at mu=7.6 (batched vs plain) + p99 event latency",
@@ -211,9 +331,23 @@ def main():
                      "k_write": round(float(stage[2]), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 6),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg), "kernel": KERNEL},
+                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg), "kernel": KERNEL,
+                     "measured_copy_GBps": round(copy_gbps, 1),
+                     "frac_of_measured_copy": round(achieved / copy_gbps, 6)},
         "n_tracks": int(got[0][-1]),
     }
+    if sq is not None:
+        # VALU issue: a wave64 instruction takes a SIMD for 4 cycles (16 lanes);
+        # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-operations/s
+        lane_ops = 64.0 * sq["SQ_INSTS_VALU"]
+        peak = 256 * 4 * 16 * 2.4e9
+        result["valu"] = {"bound": "alu", "achieved": round(lane_ops / (k_ms * 1e-3) / 1e12, 4),
+                          "peak": round(peak / 1e12, 2), "unit": "T lane-ops/s",
+                          "frac": round(lane_ops / (k_ms * 1e-3) / peak, 4),
+                          "valu_instructions_per_launch": int(sq["SQ_INSTS_VALU"]),
+                          "salu_instructions_per_launch": int(sq["SQ_INSTS_SALU"]),
+                          "lds_instructions_per_launch": int(sq["SQ_INSTS_LDS"])}
+    result["end_to_end"] = e2e
     if tuned_ms is not None:
         result["autotune_ms"] = round(tuned_ms, 4)
     if not args.no_serve:
@@ -221,6 +355,7 @@ def main():
         result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(batch, got, args.workload)
+        result["cpu_baseline_all_cores"] = cpu_par
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")

@@ -199,6 +199,16 @@ __device__ __forceinline__ T opq(T v)
     return v;
 }
 
+// A workspace pointer hidden from the optimiser (see opq) that stays known
+// as global memory, so its accesses remain global (not flat) instructions.
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ char *opq_global(char *p)
+{
+    uint64_t v = reinterpret_cast<uint64_t>(p);
+    asm volatile("" : "+s"(v));
+    return (char *)(gchar *)v;
+}
+
 // scalar parameters of the stages
 struct Prm {
     int M, rev, K, Ws, Wf, misses;
@@ -502,7 +512,7 @@ struct Ev {
 __device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N)
 {
     Ev v;
-    v.base = opq(W.base);
+    v.base = opq_global(W.base);
     v.H = opq(W.H);
     v.E = W.E;
     v.e = e;
@@ -515,7 +525,7 @@ __device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N)
 __device__ __forceinline__ Ev fresh(const Ev &v)
 {
     Ev w = v;
-    w.base = opq(v.base);
+    w.base = opq_global(v.base);
     w.H = opq(v.H);
     return w;
 }
@@ -607,15 +617,24 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     }
     __syncthreads();
     for (int s = threadIdx.x; s < N; s += B) {
-        const uint32_t key = in_lds ? lkeys[s] : at(v.keys(), s);
-        const int i = (int)(key & 0xFFFFu);
-        const int bin = (int)((in_lds ? lkeys[N + i] : at(bins_m, i)) >> 16);
-        const int lo = hist[bin], hi = hist[bin + 1];
-        int rank = lo;
-        if (in_lds)
+        // separate LDS and memory branches keep each access in its address space
+        uint32_t key;
+        int i, rank;
+        if (in_lds) {
+            key = lkeys[s];
+            i = (int)(key & 0xFFFFu);
+            const int bin = (int)(lkeys[N + i] >> 16);
+            const int lo = hist[bin], hi = hist[bin + 1];
+            rank = lo;
             for (int m = lo; m < hi; ++m) rank += lkeys[m] < key;
-        else
+        } else {
+            key = at(v.keys(), s);
+            i = (int)(key & 0xFFFFu);
+            const int bin = (int)(at(bins_m, i) >> 16);
+            const int lo = hist[bin], hi = hist[bin + 1];
+            rank = lo;
             for (int m = lo; m < hi; ++m) rank += at(v.keys(), m) < key;
+        }
         Hit16 h;
         h.x = at(X, i);
         h.y = at(Y, i);
@@ -684,7 +703,8 @@ __device__ __forceinline__ Win window(const Prm &P, const Shared<B> &S, const Ev
 template <int B>
 struct RingStage {
     static constexpr int PF = (512 + B - 1) / B;
-    Hit16 h[PF];
+    float x[PF], y[PF], z[PF];
+    uint32_t qid[PF];
     uint16_t qp[PF];
     int hi_first, hi_last;   // high bytes of the first and last phi16 (kTab when empty)
 };
@@ -716,7 +736,11 @@ __device__ __forceinline__ void ring_load(const Prm &P, const Ev &v, int u, cons
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
-            R.h[j] = at(src, i);
+            const Hit16 h = at(src, i);
+            R.x[j] = h.x;
+            R.y[j] = h.y;
+            R.z[j] = h.z;
+            R.qid[j] = h.qid;
             R.qp[j] = i > 0 ? q_of(at(src, i - 1)) : (uint16_t)0;
         }
     }
@@ -743,8 +767,13 @@ __device__ __forceinline__ void ring_store(const Prm &P, const Ev &v, int u, Sha
     for (int j = 0; j < RingStage<B>::PF; ++j) {
         const int i = (int)threadIdx.x + j * B;
         if (i < n) {
-            ring[i] = R.h[j];
-            tab_fill(tab, i, q_of(R.h[j]), R.qp[j]);
+            Hit16 h;
+            h.x = R.x[j];
+            h.y = R.y[j];
+            h.z = R.z[j];
+            h.qid = R.qid[j];
+            ring[i] = h;
+            tab_fill(tab, i, (uint16_t)(R.qid[j] & 0xFFFFu), R.qp[j]);
         }
     }
     for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work
         // the workspace base is hidden from the optimiser per event, so the
         // pointers derived from it are not hoisted out of this loop
         Work W = W0;
-        W.base = opq(W0.base);
+        W.base = opq_global(W0.base);
         W.H = opq(W0.H);
         W.E = opq(W0.E);
         if (threadIdx.x == 0) {

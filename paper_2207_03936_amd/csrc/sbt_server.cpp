@@ -12,13 +12,24 @@
 // events are admitted into free slots, so their work overlaps on the device.
 // An event's tracks depend only on its own hits, so a result is the same
 // whether the event ran alone or in a mix.
+//
+// Host work is spread over a small pool of threads owned by the server: the
+// hits of a slot's events are copied into its pinned staging when the slot
+// launches, and a completed slot's tracks are rebased per event into one
+// result block, both in parallel over events.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -39,15 +50,93 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 struct QueuedEvent {
     int64_t id;
     double t_submit;
-    std::vector<int32_t> mo;   // M+1 local offsets
-    std::vector<float> xyz;    // x[n], y[n], z[n] (owned copy)
-    const float *bx, *by, *bz; // borrowed hits (load replay), or null
+    int32_t mo[SBT_MAX_MODULES + 1];   // local offsets
+    std::vector<float> xyz;            // x[n], y[n], z[n] (owned copy)
+    const float *bx, *by, *bz;         // borrowed hits (load replay), or null
     int32_t n;
 };
 
+// an admitted event: its hits are copied into the slot's staging at launch
 struct SlotEvent {
     int64_t id;
     double t_submit;
+    int32_t base;                      // first hit in the slot
+    int32_t n;
+    const float *x, *y, *z;
+    std::vector<float> own;            // owned hits, if the event brought its own copy
+};
+
+// Runs fn(i), i in [0, n), on the pool's threads and the caller; returns when
+// every index is done.
+class Pool {
+public:
+    explicit Pool(int n_threads)
+    {
+        for (int i = 0; i < n_threads; ++i) th_.emplace_back([this] { work(); });
+    }
+    ~Pool()
+    {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    void run(int n, const std::function<void(int)> &fn)
+    {
+        if (n <= 0) return;
+        if (th_.empty() || n == 1) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            fn_ = &fn;
+            n_ = n;
+            next_.store(0);
+            finished_ = 0;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (int i; (i = next_.fetch_add(1)) < n;) fn(i);
+        std::unique_lock<std::mutex> lk(m_);
+        done_cv_.wait(lk, [this] { return finished_ == (int)th_.size(); });
+        fn_ = nullptr;
+    }
+
+private:
+    void work()
+    {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)> *fn;
+            int n;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+                fn = fn_;
+                n = n_;
+            }
+            for (int i; (i = next_.fetch_add(1)) < n;) (*fn)(i);
+            {
+                std::lock_guard<std::mutex> g(m_);
+                ++finished_;
+            }
+            done_cv_.notify_one();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)> *fn_ = nullptr;
+    int n_ = 0;
+    std::atomic<int> next_{0};
+    int finished_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
 };
 
 enum SlotState { kFree = 0, kOpen = 1, kInFlight = 2 };
@@ -73,9 +162,17 @@ struct Slot {
     std::vector<SlotEvent> events;
 };
 
-struct ResultStore {
+// tracks of a completed slot: per event, track offsets rebased to the event
+// (events' lists laid end to end) and the hit ids
+struct ResultBlock {
     std::vector<int32_t> tho;
     std::vector<int32_t> th;
+};
+
+struct ReadyResult {
+    sbt_server_result r;
+    std::shared_ptr<ResultBlock> block;
+    size_t tho_at, th_at;
 };
 
 }  // namespace
@@ -88,9 +185,9 @@ struct sbt_server {
     std::deque<QueuedEvent> queue;
     size_t max_queue;
     int open_slot;           // index of the slot admitting events, or -1
-    std::vector<ResultStore> store;
-    std::deque<sbt_server_result> ready;   // completed, not yet returned
-    std::deque<ResultStore> ready_store;
+    std::vector<std::shared_ptr<ResultBlock>> store;   // blocks of the results last returned
+    std::deque<ReadyResult> ready;                      // completed, not yet returned
+    std::unique_ptr<Pool> pool;
 };
 
 namespace {
@@ -167,8 +264,8 @@ int init_slot(Slot &s, const SlotLayout &L)
     return SBT_OK;
 }
 
-// Packs a queued event into an open slot's pinned inputs.
-void pack(sbt_server *srv, Slot &s, const QueuedEvent &q)
+// Admits a queued event into an open slot: offsets now, hits at launch.
+void pack(sbt_server *srv, Slot &s, QueuedEvent &q)
 {
     const int M = srv->params.n_modules;
     if (s.n_events == 0) {
@@ -177,17 +274,26 @@ void pack(sbt_server *srv, Slot &s, const QueuedEvent &q)
         s.t_oldest = q.t_submit;
     }
     const int32_t base = s.n_hits;
-    const float *qx = q.bx ? q.bx : q.xyz.data();
-    const float *qy = q.bx ? q.by : q.xyz.data() + q.n;
-    const float *qz = q.bx ? q.bz : q.xyz.data() + 2 * (size_t)q.n;
-    memcpy(s.hx + base, qx, sizeof(float) * q.n);
-    memcpy(s.hy + base, qy, sizeof(float) * q.n);
-    memcpy(s.hz + base, qz, sizeof(float) * q.n);
     for (int k = 1; k <= M; ++k) s.hmo[(size_t)s.n_events * M + k] = base + q.mo[k];
     s.n_hits += q.n;
     s.n_events += 1;
     s.heo[s.n_events] = s.n_hits;
-    s.events.push_back(SlotEvent{q.id, q.t_submit});
+    SlotEvent se;
+    se.id = q.id;
+    se.t_submit = q.t_submit;
+    se.base = base;
+    se.n = q.n;
+    if (q.bx) {
+        se.x = q.bx;
+        se.y = q.by;
+        se.z = q.bz;
+    } else {
+        se.own = std::move(q.xyz);
+        se.x = se.own.data();
+        se.y = se.own.data() + q.n;
+        se.z = se.own.data() + 2 * (size_t)q.n;
+    }
+    s.events.push_back(std::move(se));
 }
 
 int launch(sbt_server *srv, Slot &s)
@@ -196,6 +302,16 @@ int launch(sbt_server *srv, Slot &s)
     const SlotLayout L = slot_layout(srv->cfg, M);
     const size_t E = (size_t)s.n_events, H = (size_t)s.n_hits;
     hipStream_t st = s.stream;
+    // hits into the pinned staging, in parallel over events
+    srv->pool->run((int)s.events.size(), [&](int i) {
+        SlotEvent &ev = s.events[(size_t)i];
+        if (ev.n > 0) {
+            memcpy(s.hx + ev.base, ev.x, sizeof(float) * ev.n);
+            memcpy(s.hy + ev.base, ev.y, sizeof(float) * ev.n);
+            memcpy(s.hz + ev.base, ev.z, sizeof(float) * ev.n);
+        }
+        std::vector<float>().swap(ev.own);
+    });
     // inputs (only the used prefix of each array)
     if (H > 0) {
         if (hipMemcpyAsync(s.dx, s.hx, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
@@ -230,28 +346,37 @@ int launch(sbt_server *srv, Slot &s)
     return SBT_OK;
 }
 
-// Moves a completed slot's events to the ready queue.
+// Moves a completed slot's events to the ready queue: one result block, filled
+// in parallel over events.
 void collect(sbt_server *srv, Slot &s)
 {
     const double t = now_us();
-    for (int32_t i = 0; i < s.n_events; ++i) {
+    const int32_t E = s.n_events;
+    auto block = std::make_shared<ResultBlock>();
+    const int32_t T = s.heto[E];
+    const int32_t A = s.htho[T];
+    block->tho.resize((size_t)T + (size_t)E);
+    block->th.resize((size_t)A);
+    const size_t base = srv->ready.size();
+    srv->ready.resize(base + (size_t)E);
+    srv->pool->run(E, [&](int i) {
         const int32_t t0 = s.heto[i], t1 = s.heto[i + 1];
-        ResultStore rs;
-        rs.tho.resize((size_t)(t1 - t0) + 1);
-        const int32_t h0 = s.htho[t0];
-        for (int32_t k = t0; k <= t1; ++k) rs.tho[(size_t)(k - t0)] = s.htho[k] - h0;
-        rs.th.assign(s.hth + h0, s.hth + s.htho[t1]);
-        sbt_server_result r;
-        r.request_id = s.events[(size_t)i].id;
-        r.status = s.hst[i];
-        r.n_tracks = t1 - t0;
-        r.track_hit_offsets = nullptr;
-        r.track_hits = nullptr;
-        r.t_submit_us = s.events[(size_t)i].t_submit;
-        r.t_done_us = t;
-        srv->ready.push_back(r);
-        srv->ready_store.push_back(std::move(rs));
-    }
+        const int32_t h0 = s.htho[t0], h1 = s.htho[t1];
+        int32_t *tho = block->tho.data() + t0 + i;
+        for (int32_t k = t0; k <= t1; ++k) tho[k - t0] = s.htho[k] - h0;
+        if (h1 > h0) memcpy(block->th.data() + h0, s.hth + h0, sizeof(int32_t) * (size_t)(h1 - h0));
+        ReadyResult &rr = srv->ready[base + (size_t)i];
+        rr.r.request_id = s.events[(size_t)i].id;
+        rr.r.status = s.hst[i];
+        rr.r.n_tracks = t1 - t0;
+        rr.r.track_hit_offsets = nullptr;
+        rr.r.track_hits = nullptr;
+        rr.r.t_submit_us = s.events[(size_t)i].t_submit;
+        rr.r.t_done_us = t;
+        rr.tho_at = (size_t)t0 + (size_t)i;
+        rr.th_at = (size_t)h0;
+    });
+    for (int32_t i = 0; i < E; ++i) srv->ready[base + (size_t)i].block = block;
     s.events.clear();
     s.n_events = 0;
     s.n_hits = 0;
@@ -282,7 +407,7 @@ int step(sbt_server *srv)
             if (srv->open_slot < 0) break;   // every slot is busy: events wait on the host
         }
         Slot &s = srv->slots[(size_t)srv->open_slot];
-        const QueuedEvent &q = srv->queue.front();
+        QueuedEvent &q = srv->queue.front();
         if (s.n_events + 1 > srv->cfg.slot_events || s.n_hits + q.n > srv->cfg.slot_hits) {
             int rc = launch(srv, s);        // full: launch it and open another
             if (rc) return rc;
@@ -331,6 +456,15 @@ int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const 
     srv->cfg = c;
     srv->max_queue = (size_t)c.n_slots * (size_t)c.slot_events * 4;
     srv->open_slot = -1;
+    {
+        const unsigned hw = std::thread::hardware_concurrency();
+        const int workers = (int)std::min(7u, hw > 1 ? hw - 1 : 0u);
+        srv->pool.reset(new (std::nothrow) Pool(workers));
+        if (!srv->pool) {
+            delete srv;
+            return SBT_ERR_NOMEM;
+        }
+    }
     srv->slots.resize((size_t)c.n_slots);
     for (auto &s : srv->slots) {
         if ((rc = init_slot(s, L))) {
@@ -368,7 +502,7 @@ int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits, const
     q.t_submit = now_us();
     q.bx = q.by = q.bz = nullptr;
     q.n = n_hits;
-    q.mo.assign(module_offsets, module_offsets + M + 1);
+    for (int k = 0; k <= M; ++k) q.mo[k] = module_offsets[k];
     q.xyz.resize(3 * (size_t)n_hits);
     if (n_hits > 0) {
         memcpy(q.xyz.data(), x, sizeof(float) * n_hits);
@@ -392,15 +526,13 @@ int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_res
     }
     int32_t n = 0;
     while (n < max_results && !srv->ready.empty()) {
-        srv->store.push_back(std::move(srv->ready_store.front()));
-        srv->ready_store.pop_front();
-        results[n] = srv->ready.front();
+        ReadyResult &rr = srv->ready.front();
+        results[n] = rr.r;
+        results[n].track_hit_offsets = rr.block->tho.data() + rr.tho_at;
+        results[n].track_hits = rr.block->th.data() + rr.th_at;
+        if (srv->store.empty() || srv->store.back() != rr.block) srv->store.push_back(rr.block);
         srv->ready.pop_front();
         ++n;
-    }
-    for (int32_t i = 0; i < n; ++i) {
-        results[i].track_hit_offsets = srv->store[(size_t)i].tho.data();
-        results[i].track_hits = srv->store[(size_t)i].th.data();
     }
     return n;
 }
@@ -429,8 +561,7 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
             q.id = next;
             q.t_submit = t0 + arrival_us[next];
             q.n = hi - lo;
-            q.mo.resize((size_t)M + 1);
-            for (int k = 0; k <= M; ++k) q.mo[(size_t)k] = module_offsets[(size_t)e * M + k] - lo;
+            for (int k = 0; k <= M; ++k) q.mo[k] = module_offsets[(size_t)e * M + k] - lo;
             q.bx = x + lo;
             q.by = y + lo;
             q.bz = z + lo;
