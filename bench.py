@@ -198,9 +198,10 @@ def serving_leg(params, seconds, fraction=0.5):
     return res
 
 
-def cpu_baseline(batch, gpu_out, workload="mu7.6", target_s=12.0):
+def cpu_baseline(batch, gpu_out, workload="mu7.6", target_s=10.0):
     """The oracle as it stands, single-threaded, on a bounded sample of the
-    same events; also confirms the GPU track sets on that sample."""
+    same events (repeated passes up to about target_s); also confirms the GPU
+    track sets on that sample."""
     import oracle
     E = batch.n_events
     n = min(E, 200)
@@ -211,16 +212,21 @@ def cpu_baseline(batch, gpu_out, workload="mu7.6", target_s=12.0):
     per_event = dt / n
     n = min(E, max(n, int(target_s / max(per_event, 1e-6))))
     sub = batch.select(range(n))
+    passes, done = 0, 0.0
     t = time.perf_counter()
-    want = oracle.reconstruct(sub)
-    dt = time.perf_counter() - t
+    while True:
+        want = oracle.reconstruct(sub)
+        passes += 1
+        done = time.perf_counter() - t
+        if done >= 0.9 * target_s:
+            break
     eto, tho, th = gpu_out[:3]
     T = int(eto[n])
     ok = (np.array_equal(eto[:n + 1], want[0]) and np.array_equal(tho[:T + 1], want[1])
           and np.array_equal(th[:int(tho[T])], want[2]))
-    return dict(value=round(n / dt, 2), unit="events/s", cores=1, kind="oracle",
-                sample=f"first {n} events of the {workload} batch, one pass, single thread",
-                hits_per_s=round(int(sub.n_hits) / dt, 1), gpu_matches_oracle_on_sample=bool(ok))
+    return dict(value=round(passes * n / done, 2), unit="events/s", cores=1, kind="oracle",
+                sample=f"first {n} events of the {workload} batch, {passes} pass(es), single thread",
+                hits_per_s=round(passes * int(sub.n_hits) / done, 1), gpu_matches_oracle_on_sample=bool(ok))
 
 
 def main():
