@@ -52,7 +52,7 @@ def algorithmic_bytes(batch, eto, tho) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sbt_device.h", "sbt.hip"):
+    for f in ("sbt_device.h", "sbt.hip", "sbt_persistent.hip", "sbt_kernels.h"):
         with open(os.path.join(ROOT, "paper_2207_03936_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
