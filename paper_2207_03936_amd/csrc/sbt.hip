@@ -74,7 +74,7 @@ __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
         return;
     }
     const int hb = H.eo[e];
-    stage_compact<B>(event_view(W, e, hb, H.eo[e + 1] - hb), scan);
+    stage_compact<B>(event_view(W, e, hb, H.eo[e + 1] - hb), scan, 0);
 }
 
 // batched form ----------------------------------------------------------------

@@ -569,8 +569,14 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
 // Counting sort on (module, top bits of phi16) into buckets of 32-bit keys
 // phi16 << 16 | id, then each key's rank inside its bucket by counting the
 // smaller keys of the bucket; ties in phi16 fall to the lower id because the
-// id is the key's low half.  Keys and per-hit bins live in LDS when the
-// event has at most sortcap/2 hits, else in memory.
+// id is the key's low half.  Three forms by event size against the LDS key
+// capacity sortcap: keys and per-hit bins in LDS (2N <= sortcap); keys in
+// LDS with the bins recomputed (N <= sortcap); both in memory.
+__device__ __forceinline__ int sort_bin(const int *mo, int M, int i, uint16_t q, int bpm, int shift)
+{
+    return module_of(mo, M, i) * bpm + (q >> shift);
+}
+
 template <int B>
 __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0, Shared<B> &S, int sortcap)
 {
@@ -582,31 +588,38 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     int *hist = reinterpret_cast<int *>(g_lds);
     int *fill = hist + kSortBins + 1;
     uint32_t *lkeys = reinterpret_cast<uint32_t *>(g_lds + lds_sort_head());
-    const bool in_lds = 2 * N <= sortcap;
+    const int form = 2 * N <= sortcap ? 0 : (N <= sortcap ? 1 : 2);
     for (int i = threadIdx.x; i <= nb; i += B) hist[i] = 0;
     for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
     __syncthreads();
     const float *__restrict__ X = H.x + v.hb;
     const float *__restrict__ Y = H.y + v.hb;
     const float *__restrict__ Z = H.z + v.hb;
-    // bins: LDS after the keys, or the claim words (not yet in use) in memory
+    // memory form: bins in the claim words (not yet in use)
     uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
     for (int i = threadIdx.x; i < N; i += B) {
         const uint16_t qi = phi16(at(X, i), at(Y, i));
-        const int bin = module_of(S.mo, M, i) * bpm + (qi >> shift);
+        const int bin = sort_bin(S.mo, M, i, qi, bpm, shift);
         const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
-        if (in_lds) lkeys[N + i] = tb;
-        else at(bins_m, i) = tb;
+        if (form == 0) lkeys[N + i] = tb;
+        else if (form == 2) at(bins_m, i) = tb;
         atomicAdd(&hist[bin], 1);
     }
     __syncthreads();
     block_scan_inplace<B>(hist, nb + 1, S.scan);
     __syncthreads();
-    if (in_lds) {
+    // separate LDS and memory branches keep each access in its address space
+    if (form == 0) {
         for (int i = threadIdx.x; i < N; i += B) {
             const uint32_t tb = lkeys[N + i];
             const int bin = (int)(tb >> 16);
             lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = (tb << 16) | (uint32_t)i;
+        }
+    } else if (form == 1) {
+        for (int i = threadIdx.x; i < N; i += B) {
+            const uint16_t qi = phi16(at(X, i), at(Y, i));
+            const int bin = sort_bin(S.mo, M, i, qi, bpm, shift);
+            lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
         }
     } else {
         for (int i = threadIdx.x; i < N; i += B) {
@@ -617,13 +630,13 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     }
     __syncthreads();
     for (int s = threadIdx.x; s < N; s += B) {
-        // separate LDS and memory branches keep each access in its address space
         uint32_t key;
         int i, rank;
-        if (in_lds) {
+        if (form != 2) {
             key = lkeys[s];
             i = (int)(key & 0xFFFFu);
-            const int bin = (int)(lkeys[N + i] >> 16);
+            const int bin = form == 0 ? (int)(lkeys[N + i] >> 16)
+                                      : sort_bin(S.mo, M, i, (uint16_t)(key >> 16), bpm, shift);
             const int lo = hist[bin], hi = hist[bin + 1];
             rank = lo;
             for (int m = lo; m < hi; ++m) rank += lkeys[m] < key;
@@ -1378,10 +1391,18 @@ __device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, cons
 // Accepted tracks in key order: per-event track offsets and hit ids into the
 // staging arrays, counts into the event's counters.
 template <int B>
-__device__ void stage_compact(const Ev &v0, int *s_scan)
+__device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
 {
     const Ev v = fresh(v0);
     const int N = v.N;
+    // the previous-hit links in LDS (free after the tracking stages) when
+    // they fit, so that the chain walk below costs LDS latency per hop
+    uint16_t *lprev = reinterpret_cast<uint16_t *>(g_lds);
+    const bool in_lds = 2 * N <= lds_bytes;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < N; i += B) lprev[i] = at(v.link(), 2u * i);
+        __syncthreads();
+    }
     int tcarry = 0, hcarry = 0;
     bool bad = false;
     int phase = 0;
@@ -1405,10 +1426,18 @@ __device__ void stage_compact(const Ev &v0, int *s_scan)
                 at(v.st_toff(), ti) = hi;
                 uint16_t *out = v.st_hits() + hi;
                 uint16_t p = R.last;
-                for (int j = R.len - 1; j >= 3; --j) {
-                    if (p >= N) { bad = true; break; }
-                    out[j] = p;
-                    p = at(v.link(), 2u * p);
+                if (in_lds) {
+                    for (int j = R.len - 1; j >= 3; --j) {
+                        if (p >= N) { bad = true; break; }
+                        out[j] = p;
+                        p = lprev[p];
+                    }
+                } else {
+                    for (int j = R.len - 1; j >= 3; --j) {
+                        if (p >= N) { bad = true; break; }
+                        out[j] = p;
+                        p = at(v.link(), 2u * p);
+                    }
                 }
                 out[2] = R.h2;
                 out[1] = R.h1;

@@ -41,7 +41,7 @@ __global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work
             const int n_fin = uni(S.cnt[3]);
             if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own());
             else stage_filter<B>(P, v, n_fin, v.own());
-            stage_compact<B>(v, S.scan);
+            stage_compact<B>(v, S.scan, (int)lds_sort_head() + 4 * sortcap);
         } else if (threadIdx.x == 0) {
             ws_evinfo(W)[e].nt = 0;
             ws_evinfo(W)[e].nh = 0;
