@@ -1401,58 +1401,60 @@ __device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
     const bool in_lds = 2 * N <= lds_bytes;
     if (in_lds) {
         for (int i = threadIdx.x; i < N; i += B) lprev[i] = at(v.link(), 2u * i);
-        __syncthreads();
     }
-    int tcarry = 0, hcarry = 0;
-    bool bad = false;
-    int phase = 0;
-    for (int base = 0; base < N; base += B, ++phase) {
-        const int key = base + (int)threadIdx.x;
-        const uint16_t r = key < N ? at(v.link(), 2u * key + 1u) : kNone;
-        Rec R;
-        int len = 0;
+    // each lane owns a contiguous range of keys: count its tracks and hits,
+    // one scan of each over the workgroup, then write them in key order
+    const int per = (N + B - 1) / B;
+    const int k0 = min(N, (int)threadIdx.x * per), k1 = min(N, k0 + per);
+    int nt = 0, nh = 0;
+    for (int k = k0; k < k1; ++k) {
+        const uint16_t r = at(v.link(), 2u * k + 1u);
         if (r != kNone) {
-            R = at(v.rec(), r);
-            len = R.len;
+            ++nt;
+            nh += at(v.rec(), r).len;
         }
-        int total;
-        const int ex = block_excl_scan<B>((r != kNone ? (1 << 16) : 0) | len, s_scan, phase, &total);
-        if (r != kNone) {
-            const int ti = tcarry + (ex >> 16);
-            const int hi = hcarry + (ex & 0xFFFF);
-            // tracks are disjoint, so hi + len <= N; the checks below only
-            // keep a broken invariant from turning into a stray access
-            if (hi + R.len <= N) {
-                at(v.st_toff(), ti) = hi;
-                uint16_t *out = v.st_hits() + hi;
-                uint16_t p = R.last;
-                if (in_lds) {
-                    for (int j = R.len - 1; j >= 3; --j) {
-                        if (p >= N) { bad = true; break; }
-                        out[j] = p;
-                        p = lprev[p];
-                    }
-                } else {
-                    for (int j = R.len - 1; j >= 3; --j) {
-                        if (p >= N) { bad = true; break; }
-                        out[j] = p;
-                        p = at(v.link(), 2u * p);
-                    }
-                }
-                out[2] = R.h2;
-                out[1] = R.h1;
-                out[0] = R.h0;
-            } else {
-                bad = true;
+    }
+    int tt, th;
+    int ti = block_excl_scan<B>(nt, s_scan, 0, &tt);
+    int hi = block_excl_scan<B>(nh, s_scan, 1, &th);
+    __syncthreads();   // LDS links visible
+    bool bad = th > N;
+    for (int k = k0; k < k1 && !bad; ++k) {
+        const uint16_t r = at(v.link(), 2u * k + 1u);
+        if (r == kNone) continue;
+        const Rec R = at(v.rec(), r);
+        // tracks are disjoint, so hi + len <= N; the checks below only keep a
+        // broken invariant from turning into a stray access
+        if (hi + R.len > N) {
+            bad = true;
+            break;
+        }
+        at(v.st_toff(), ti) = hi;
+        uint16_t *out = v.st_hits() + hi;
+        uint16_t p = R.last;
+        if (in_lds) {
+            for (int j = R.len - 1; j >= 3; --j) {
+                if (p >= N) { bad = true; break; }
+                out[j] = p;
+                p = lprev[p];
+            }
+        } else {
+            for (int j = R.len - 1; j >= 3; --j) {
+                if (p >= N) { bad = true; break; }
+                out[j] = p;
+                p = at(v.link(), 2u * p);
             }
         }
-        tcarry += total >> 16;
-        hcarry += total & 0xFFFF;
+        out[2] = R.h2;
+        out[1] = R.h1;
+        out[0] = R.h0;
+        ++ti;
+        hi += R.len;
     }
     if (bad) v.info().st = (int)SBT_EV_INTERNAL;
     if (threadIdx.x == 0) {
-        v.info().nt = hcarry <= N ? tcarry : 0;
-        v.info().nh = hcarry <= N ? hcarry : 0;
+        v.info().nt = th <= N ? tt : 0;
+        v.info().nh = th <= N ? th : 0;
     }
 }
 
