@@ -474,6 +474,7 @@ struct Shared {
     int ovf;             // an LDS list overflowed
     int scan[2 * (B / 64)];
     int slot_n[4];       // hits of the module held by each ring slot
+    uint8_t mtab[(SBT_MAX_EVENT_HITS + 64) / 64];   // module of every 64th hit (sort)
 };
 
 // per-event views of the workspace: pointers are derived on use from the
@@ -572,9 +573,12 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
 // id is the key's low half.  Three forms by event size against the LDS key
 // capacity sortcap: keys and per-hit bins in LDS (2N <= sortcap); keys in
 // LDS with the bins recomputed (N <= sortcap); both in memory.
-__device__ __forceinline__ int sort_bin(const int *mo, int M, int i, uint16_t q, int bpm, int shift)
+// module of hit i from the module of its 64-hit chunk and a short forward scan
+__device__ __forceinline__ int sort_bin(const int *mo, const uint8_t *mtab, int i, uint16_t q, int bpm, int shift)
 {
-    return module_of(mo, M, i) * bpm + (q >> shift);
+    int m = mtab[i >> 6];
+    while (mo[m + 1] <= i) ++m;
+    return m * bpm + (q >> shift);
 }
 
 template <int B>
@@ -591,6 +595,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     const int form = 2 * N <= sortcap ? 0 : (N <= sortcap ? 1 : 2);
     for (int i = threadIdx.x; i <= nb; i += B) hist[i] = 0;
     for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
+    for (int c = threadIdx.x; c < (N + 63) / 64; c += B) S.mtab[c] = (uint8_t)module_of(S.mo, M, c * 64);
     __syncthreads();
     const float *__restrict__ X = H.x + v.hb;
     const float *__restrict__ Y = H.y + v.hb;
@@ -599,7 +604,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
     for (int i = threadIdx.x; i < N; i += B) {
         const uint16_t qi = phi16(at(X, i), at(Y, i));
-        const int bin = sort_bin(S.mo, M, i, qi, bpm, shift);
+        const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
         const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
         if (form == 0) lkeys[N + i] = tb;
         else if (form == 2) at(bins_m, i) = tb;
@@ -618,7 +623,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     } else if (form == 1) {
         for (int i = threadIdx.x; i < N; i += B) {
             const uint16_t qi = phi16(at(X, i), at(Y, i));
-            const int bin = sort_bin(S.mo, M, i, qi, bpm, shift);
+            const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
             lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
         }
     } else {
@@ -636,7 +641,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
             key = lkeys[s];
             i = (int)(key & 0xFFFFu);
             const int bin = form == 0 ? (int)(lkeys[N + i] >> 16)
-                                      : sort_bin(S.mo, M, i, (uint16_t)(key >> 16), bpm, shift);
+                                      : sort_bin(S.mo, S.mtab, i, (uint16_t)(key >> 16), bpm, shift);
             const int lo = hist[bin], hi = hist[bin + 1];
             rank = lo;
             for (int m = lo; m < hi; ++m) rank += lkeys[m] < key;
