@@ -149,7 +149,7 @@ typedef struct sbt_tracks {
 } sbt_tracks;
 
 /* Launch configuration of the batched path.  It never changes results.
- * threads_per_event   64, 128, 256 or 512 lanes cooperating on one event.
+ * threads_per_event   64, 128, 256, 512 or 1024 lanes cooperating on one event.
  * blocks_per_cu       persistent workgroups per compute unit (1..16).
  * lds_window_hits     capacity, in hits, of each of the four LDS slots that
  *                     hold the phi-sorted hits of consecutive modules

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libsbt.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SBT_OFFLOAD_ARCH", "gfx950")
 # persistent kernels: one translation unit per workgroup width, built in parallel
-WIDTHS = (64, 128, 256, 512)
+WIDTHS = (64, 128, 256, 512, 1024)
 
 
 def hipcc() -> str:

@@ -186,7 +186,7 @@ size_t carve(int32_t E, int32_t H, char *base, Work *W)
     return (size_t)ws_bytes(h, e);
 }
 
-bool is_pow_tpe(int v) { return v == 64 || v == 128 || v == 256 || v == 512; }
+bool is_pow_tpe(int v) { return v == 64 || v == 128 || v == 256 || v == 512 || v == 1024; }
 
 // dynamic LDS a workgroup may ask for (gfx950: 160 KiB per compute unit)
 constexpr size_t kMaxDynLds = 160 * 1024 - 1024;
@@ -271,6 +271,7 @@ const void *persistent_kernel(int tpe, int cap)
     case 128: return persistent_kernel_128(cap);
     case 256: return persistent_kernel_256(cap);
     case 512: return persistent_kernel_512(cap);
+    case 1024: return persistent_kernel_1024(cap);
     default: return nullptr;
     }
 }
@@ -665,7 +666,7 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
     }
     // candidates: lanes per event x LDS slot capacity, each at the largest
     // number of resident workgroups per CU and one less
-    const int tpes[] = {128, 256, 512};
+    const int tpes[] = {128, 256, 512, 1024};
     const int caps[] = {256, 448, 672, 1024, 1536};
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;

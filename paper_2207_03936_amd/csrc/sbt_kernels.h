@@ -15,5 +15,6 @@ const void *persistent_kernel_64(int cap);
 const void *persistent_kernel_128(int cap);
 const void *persistent_kernel_256(int cap);
 const void *persistent_kernel_512(int cap);
+const void *persistent_kernel_1024(int cap);
 
 }  // namespace sbt

@@ -107,7 +107,7 @@ def test_batched_matches_oracle(config, n):
     _same(got, want, f"batched {config}")
 
 
-@pytest.mark.parametrize("tpe", [64, 128, 256, 512])
+@pytest.mark.parametrize("tpe", [64, 128, 256, 512, 1024])
 @pytest.mark.parametrize("bpc", [1, 3, 8])
 def test_batched_independent_of_launch_configuration(tpe, bpc):
     say(f"batched tuning tpe={tpe} bpc={bpc}")
@@ -119,7 +119,8 @@ def test_batched_independent_of_launch_configuration(tpe, bpc):
 
 # LDS capacities: 0 or 1 forces every module window / the owner flags to be
 # read from memory, intermediate values mix both within one event
-LDS_CASES = [(0, 0), (1, 1), (64, 1000), (200, 3000), (672, 16384), (1024, 65536), (1536, 0)]
+LDS_CASES = [(0, 0), (1, 1), (64, 1000), (200, 3000), (256, 16384), (448, 16384), (672, 16384),
+             (1024, 65536), (1536, 0)]
 
 
 @pytest.mark.parametrize("cap,own", LDS_CASES)
@@ -128,7 +129,7 @@ def test_lds_overflow_fallbacks(cap, own, config, n):
     say(f"lds cap={cap} own={own} {config} x{n}")
     b = synth.make_batch(config, n, first=7)
     want = oracle.reconstruct(b)
-    for tpe in (64, 256):
+    for tpe in (64, 256, 1024):
         _same(run_batched(b, sbt.make_tuning(tpe, 2, cap, own)), want, f"cap={cap} own={own} tpe={tpe}")
 
 
