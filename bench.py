@@ -103,45 +103,67 @@ def copy_bandwidth(torch, mib=1024, reps=10):
     return 2 * 4 * n / sec / 1e9
 
 
-def end_to_end(torch, sbt, ctx, batch, steps):
+def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False):
     """Whole-batch rate with the hits in pinned host memory at the start and
-    the tracks back in pinned host memory at the end (H2D, reconstruction and
-    D2H on one stream)."""
+    the tracks back in pinned host memory at the end.  Sequential: H2D,
+    reconstruction and D2H on one stream.  Pipelined: two contexts on two
+    streams, so the copies of one batch overlap the reconstruction of the
+    other."""
     def pinned(a, dt):
-        t = torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
-        return t
-    hx, hy, hz = pinned(batch.x, np.float32), pinned(batch.y, np.float32), pinned(batch.z, np.float32)
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
     heo, hmo = pinned(batch.event_offsets, np.int32), pinned(batch.module_offsets, np.int32)
-    dev = sbt.DeviceBatch(batch)
-    out = sbt.DeviceTracks(batch.n_events, batch.n_hits)
-    ctx.reconstruct(dev, out)
+    E, H = batch.n_events, batch.n_hits
+    lanes = 2 if pipelined else 1
+    ctxs = [sbt.Context(params, E, H, tuning) for _ in range(lanes)]
+    if f16:
+        xyzw = sbt.to_f16_aos(batch.x, batch.y, batch.z)
+        hcoords = [pinned(xyzw.reshape(-1).view(np.int16), np.int16)]
+        devs = [sbt.DeviceBatchF16(batch, xyzw) for _ in range(lanes)]
+        coords = lambda dev: [dev.xyzw]
+        run = lambda c, dev, out, st: c.reconstruct_f16(dev, out, st)
+        coord_bytes = 8 * H
+    else:
+        hcoords = [pinned(batch.x, np.float32), pinned(batch.y, np.float32), pinned(batch.z, np.float32)]
+        devs = [sbt.DeviceBatch(batch) for _ in range(lanes)]
+        coords = lambda dev: [dev.x, dev.y, dev.z]
+        run = lambda c, dev, out, st: c.reconstruct(dev, out, st)
+        coord_bytes = 12 * H
+    outs = [sbt.DeviceTracks(E, H) for _ in range(lanes)]
+    streams = [torch.cuda.Stream() for _ in range(lanes)] if pipelined else [torch.cuda.current_stream()]
+    run(ctxs[0], devs[0], outs[0], torch.cuda.current_stream())
     torch.cuda.synchronize()
-    T = int(out.eto[-1].item())
-    A = int(out.tho[T].item())
-    oeto = torch.empty(batch.n_events + 1, dtype=torch.int32).pin_memory()
-    otho = torch.empty(T + 1, dtype=torch.int32).pin_memory()
-    oth = torch.empty(max(A, 1), dtype=torch.int32).pin_memory()
+    T = int(outs[0].eto[-1].item())
+    A = int(outs[0].tho[T].item())
+    hout = [(torch.empty(E + 1, dtype=torch.int32).pin_memory(), torch.empty(T + 1, dtype=torch.int32).pin_memory(),
+             torch.empty(max(A, 1), dtype=torch.int32).pin_memory()) for _ in range(lanes)]
 
-    def step():
-        for d, h in ((dev.x, hx), (dev.y, hy), (dev.z, hz), (dev.eo, heo), (dev.mo, hmo)):
-            d.copy_(h, non_blocking=True)
-        ctx.reconstruct(dev, out)
-        oeto.copy_(out.eto, non_blocking=True)
-        otho.copy_(out.tho[:T + 1], non_blocking=True)
-        oth[:A].copy_(out.th[:A], non_blocking=True)
-    for _ in range(3):
-        step()
+    def step(k):
+        i = k % lanes
+        dev, out, (oeto, otho, oth), st = devs[i], outs[i], hout[i], streams[i]
+        with torch.cuda.stream(st):
+            for d, h in list(zip(coords(dev), hcoords)) + [(dev.eo, heo), (dev.mo, hmo)]:
+                d.copy_(h, non_blocking=True)
+            run(ctxs[i], dev, out, st)
+            oeto.copy_(out.eto, non_blocking=True)
+            otho.copy_(out.tho[:T + 1], non_blocking=True)
+            oth[:A].copy_(out.th[:A], non_blocking=True)
+    for k in range(2 * lanes):
+        step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
+    for k in range(steps):
+        step(k)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
-    in_bytes = 12 * batch.n_hits + 4 * (batch.n_events + 1) + 4 * batch.module_offsets.shape[0]
-    out_bytes = 4 * (batch.n_events + 1) + 4 * (T + 1) + 4 * A
-    return dict(events_per_s=round(batch.n_events / sec, 1), ms_per_step=round(sec * 1e3, 4),
+    for c in ctxs:
+        c.close()
+    in_bytes = coord_bytes + 4 * (E + 1) + 4 * batch.module_offsets.shape[0]
+    out_bytes = 4 * (E + 1) + 4 * (T + 1) + 4 * A
+    return dict(events_per_s=round(E / sec, 1), ms_per_step=round(sec * 1e3, 4),
                 pcie_bytes_per_step=int(in_bytes + out_bytes),
-                note="hits in pinned host memory before, tracks in pinned host memory after")
+                note=("two contexts on two streams: copies of one batch overlap the reconstruction of the other"
+                      if pipelined else "H2D, reconstruction and D2H on one stream") +
+                     "; hits in pinned host memory before, tracks in pinned host memory after")
 
 
 def _oracle_slice(args):
@@ -311,7 +333,15 @@ def main():
     traffic = measured_traffic(H)
     copy_gbps = copy_bandwidth(torch)
     sq = measured_sq(H)
-    e2e = end_to_end(torch, sbt, ctx, batch, max(5, min(args.steps, 20)))
+    e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
+    e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True)
+    # half-precision array-of-structures input (the paper's hit-storage optimisation)
+    dev16 = sbt.DeviceBatchF16(batch)
+    out16 = sbt.DeviceTracks(E, H)
+    sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16), args.steps, args.warmup)
+    got16 = out16.to_host()
+    e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True)
+    del dev16, out16
 
     result = {
         "metric": "events/s on 1 MI355X at mu=7.6 (batched vs plain) + p99 event latency",
@@ -354,6 +384,12 @@ def main():
                           "salu_instructions_per_launch": int(sq["SQ_INSTS_SALU"]),
                           "lds_instructions_per_launch": int(sq["SQ_INSTS_LDS"])}
     result["end_to_end"] = e2e
+    result["end_to_end_pipelined"] = e2e_p
+    result["f16_aos"] = {"events_per_s": round(E / sec_f16, 1), "ms_per_step": round(sec_f16 * 1e3, 4),
+                         "input_bytes_per_hit": 8, "n_tracks": int(got16[0][-1]),
+                         "end_to_end_pipelined": e2e_f16,
+                         "note": "binary16 x, y, z, unused per hit, widened exactly on load; tracks equal the "
+                                 "binary32 path on the rounded coordinates (GPU parity tests)"}
     if tuned_ms is not None:
         result["autotune_ms"] = round(tuned_ms, 4)
     if not args.no_serve:

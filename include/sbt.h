@@ -132,6 +132,22 @@ typedef struct sbt_hits {
     const float *z;
 } sbt_hits;
 
+/* Input batch with half-precision coordinates in array-of-structures form,
+ * the paper's storage optimisation for hit coordinates (Section 4,
+ * optimisation table: fp-16 and AOS for VELO hit coordinates).
+ * xyzw            [4*n_hits] binary16 bit patterns, hit i at 4i: x, y, z and
+ *                 one unused value (8 bytes per hit instead of 12).
+ * Offsets as in sbt_hits.  Coordinates are widened to binary32 exactly when
+ * loaded and every computation is the binary32 one of sbt_hits, so the
+ * result equals sbt_reconstruct_batched on the binary16 values widened.  */
+typedef struct sbt_hits_f16 {
+    int32_t n_events;
+    int32_t n_hits;
+    const int32_t *event_offsets;
+    const int32_t *module_offsets;
+    const uint16_t *xyzw;
+} sbt_hits_f16;
+
 /* Output (device pointers), CSR over events and tracks.  Capacities follow
  * from the method: tracks are disjoint and have >= 3 hits.
  * event_track_offsets [n_events+1]: tracks of event e are
@@ -212,6 +228,10 @@ int sbt_context_get_tuning(const sbt_context *ctx, sbt_tuning *out);
  * Same outputs as sbt_reconstruct, byte for byte.                        */
 int sbt_reconstruct_batched(sbt_context *ctx, const sbt_hits *hits, sbt_tracks *tracks,
                             void *stream);
+
+/* sbt_reconstruct_batched for half-precision array-of-structures hits
+ * (sbt_hits_f16).  Same errors; xyzw must be 8-byte aligned.             */
+int sbt_reconstruct_batched_f16(sbt_context *ctx, const sbt_hits_f16 *hits, sbt_tracks *tracks, void *stream);
 
 /* Time the candidate launch configurations on `sample` (reps launches each,
  * after one warm-up) and install the fastest in the context.  `tracks` is

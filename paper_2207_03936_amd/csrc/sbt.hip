@@ -216,6 +216,28 @@ HitsArgs hits_args(const sbt_hits *h)
     a.x = h->x;
     a.y = h->y;
     a.z = h->z;
+    a.h16 = nullptr;
+    return a;
+}
+
+int check_hits_f16(const sbt_hits_f16 *h)
+{
+    if (!h) return SBT_ERR_INVALID_ARG;
+    if (h->n_events < 0 || h->n_hits < 0) return SBT_ERR_INVALID_ARG;
+    if (h->n_events > 0 && (!h->event_offsets || !h->module_offsets)) return SBT_ERR_INVALID_ARG;
+    if (h->n_hits > 0 && (!h->xyzw || ((uintptr_t)h->xyzw & 7))) return SBT_ERR_INVALID_ARG;
+    return SBT_OK;
+}
+
+HitsArgs hits_args_f16(const sbt_hits_f16 *h)
+{
+    HitsArgs a;
+    a.n_events = h->n_events;
+    a.n_hits = h->n_hits;
+    a.eo = h->event_offsets;
+    a.mo = h->module_offsets;
+    a.x = a.y = a.z = nullptr;
+    a.h16 = reinterpret_cast<const uint2 *>(h->xyzw);
     return a;
 }
 
@@ -504,8 +526,8 @@ int valid_tuning(const sbt_tuning &t)
 sbt_tuning default_tuning()
 {
     sbt_tuning t;
-    t.threads_per_event = 256;
-    t.blocks_per_cu = 3;
+    t.threads_per_event = 512;
+    t.blocks_per_cu = 2;
     t.lds_window_hits = 672;
     t.lds_owner_hits = 16384;
     return t;
@@ -595,14 +617,16 @@ int sbt_context_stage_ms(sbt_context *c, float *ms, int32_t n)
     return SBT_OK;
 }
 
-int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tracks, void *stream)
+}  // extern "C"
+
+namespace {
+
+int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
 {
-    if (!c) return SBT_ERR_INVALID_ARG;
     int rc;
-    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
-    if (hits->n_events > c->max_events || hits->n_hits > c->max_hits) return SBT_ERR_WORKSPACE;
+    if ((rc = check_tracks(tracks))) return rc;
+    if (H.n_events > c->max_events || H.n_hits > c->max_hits) return SBT_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
-    const HitsArgs H = hits_args(hits);
     const OutArgs O = out_args(tracks);
     if (H.n_events == 0) {
         hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
@@ -615,7 +639,8 @@ int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tr
     }
     std::vector<uintptr_t> key = {
         (uintptr_t)H.n_events, (uintptr_t)H.n_hits, (uintptr_t)H.eo, (uintptr_t)H.mo, (uintptr_t)H.x,
-        (uintptr_t)H.y, (uintptr_t)H.z, (uintptr_t)O.eto, (uintptr_t)O.tho, (uintptr_t)O.th, (uintptr_t)O.status};
+        (uintptr_t)H.y, (uintptr_t)H.z, (uintptr_t)H.h16, (uintptr_t)O.eto, (uintptr_t)O.tho, (uintptr_t)O.th,
+        (uintptr_t)O.status};
     ++c->clock;
     for (auto &g : c->graphs) {
         if (g.key == key) {
@@ -645,6 +670,26 @@ int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tr
     c->graphs.push_back(GraphEntry{key, exec, c->clock});
     HIP_TRY(hipGraphLaunch(exec, s));
     return SBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tracks, void *stream)
+{
+    if (!c) return SBT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_hits(hits))) return rc;
+    return batched(c, hits_args(hits), tracks, stream);
+}
+
+int sbt_reconstruct_batched_f16(sbt_context *c, const sbt_hits_f16 *hits, sbt_tracks *tracks, void *stream)
+{
+    if (!c) return SBT_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_hits_f16(hits))) return rc;
+    return batched(c, hits_args_f16(hits), tracks, stream);
 }
 
 int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, void *stream, int32_t reps,

@@ -115,7 +115,8 @@ struct HitsArgs {
     int32_t n_hits;
     const int32_t *eo;
     const int32_t *mo;
-    const float *x, *y, *z;
+    const float *x, *y, *z;   // binary32 structure of arrays, or
+    const uint2 *h16;         // binary16 x, y, z, unused per hit (null for binary32)
 };
 
 struct OutArgs {
@@ -566,6 +567,53 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
     return uni(S.status);
 }
 
+// ---------------------------------------------------------------- hit coordinates
+// Coordinates of event-local hit i, from binary32 arrays or widened exactly
+// from the binary16 array-of-structures form.
+__device__ __forceinline__ float half_bits_to_float(uint32_t b)
+{
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(b & 0xFFFFu));
+}
+
+struct HitSrc {
+    const float *x, *y, *z;
+    const uint2 *h16;
+    __device__ __forceinline__ void xy(int i, float &px, float &py) const
+    {
+        if (h16) {
+            const uint2 w = at(h16, i);
+            px = half_bits_to_float(w.x);
+            py = half_bits_to_float(w.x >> 16);
+        } else {
+            px = at(x, i);
+            py = at(y, i);
+        }
+    }
+    __device__ __forceinline__ void xyz(int i, float &px, float &py, float &pz) const
+    {
+        if (h16) {
+            const uint2 w = at(h16, i);
+            px = half_bits_to_float(w.x);
+            py = half_bits_to_float(w.x >> 16);
+            pz = half_bits_to_float(w.y);
+        } else {
+            px = at(x, i);
+            py = at(y, i);
+            pz = at(z, i);
+        }
+    }
+};
+
+__device__ __forceinline__ HitSrc hit_src(const HitsArgs &H, int hb)
+{
+    HitSrc s;
+    s.h16 = H.h16 ? H.h16 + hb : nullptr;
+    s.x = H.h16 ? nullptr : H.x + hb;
+    s.y = H.h16 ? nullptr : H.y + hb;
+    s.z = H.h16 ? nullptr : H.z + hb;
+    return s;
+}
+
 // ---------------------------------------------------------------- sort by phi
 // Counting sort on (module, top bits of phi16) into buckets of 32-bit keys
 // phi16 << 16 | id, then each key's rank inside its bucket by counting the
@@ -597,13 +645,13 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
     for (int c = threadIdx.x; c < (N + 63) / 64; c += B) S.mtab[c] = (uint8_t)module_of(S.mo, M, c * 64);
     __syncthreads();
-    const float *__restrict__ X = H.x + v.hb;
-    const float *__restrict__ Y = H.y + v.hb;
-    const float *__restrict__ Z = H.z + v.hb;
+    const HitSrc src = hit_src(H, v.hb);
     // memory form: bins in the claim words (not yet in use)
     uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
     for (int i = threadIdx.x; i < N; i += B) {
-        const uint16_t qi = phi16(at(X, i), at(Y, i));
+        float px, py;
+        src.xy(i, px, py);
+        const uint16_t qi = phi16(px, py);
         const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
         const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
         if (form == 0) lkeys[N + i] = tb;
@@ -622,7 +670,9 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
         }
     } else if (form == 1) {
         for (int i = threadIdx.x; i < N; i += B) {
-            const uint16_t qi = phi16(at(X, i), at(Y, i));
+            float px, py;
+            src.xy(i, px, py);
+            const uint16_t qi = phi16(px, py);
             const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
             lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
         }
@@ -654,9 +704,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
             for (int m = lo; m < hi; ++m) rank += at(v.keys(), m) < key;
         }
         Hit16 h;
-        h.x = at(X, i);
-        h.y = at(Y, i);
-        h.z = at(Z, i);
+        src.xyz(i, h.x, h.y, h.z);
         h.qid = (key >> 16) | (key << 16);
         at(v.hs(), rank) = h;
     }

@@ -63,6 +63,12 @@ class SbtHits(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
 
 
+class SbtHitsF16(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_int32), ("n_hits", ctypes.c_int32),
+                ("event_offsets", ctypes.c_void_p), ("module_offsets", ctypes.c_void_p),
+                ("xyzw", ctypes.c_void_p)]
+
+
 class SbtTracks(ctypes.Structure):
     _fields_ = [("event_track_offsets", ctypes.c_void_p), ("track_hit_offsets", ctypes.c_void_p),
                 ("track_hits", ctypes.c_void_p), ("event_status", ctypes.c_void_p)]
@@ -105,6 +111,7 @@ PROTOTYPES = {
     "sbt_context_set_tuning": (ctypes.c_int, [_VP, _P(SbtTuning)]),
     "sbt_context_get_tuning": (ctypes.c_int, [_VP, _P(SbtTuning)]),
     "sbt_reconstruct_batched": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP]),
+    "sbt_reconstruct_batched_f16": (ctypes.c_int, [_VP, _P(SbtHitsF16), _P(SbtTracks), _VP]),
     "sbt_autotune": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP, ctypes.c_int32, _P(SbtTuning),
                                     _P(ctypes.c_float)]),
     "sbt_context_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int32]),
@@ -167,7 +174,7 @@ def make_params(module_z, **overrides) -> SbtParams:
     return sp
 
 
-def make_tuning(threads_per_event=256, blocks_per_cu=3, lds_window_hits=672, lds_owner_hits=16384) -> SbtTuning:
+def make_tuning(threads_per_event=512, blocks_per_cu=2, lds_window_hits=672, lds_owner_hits=16384) -> SbtTuning:
     t = SbtTuning()
     t.threads_per_event = threads_per_event
     t.blocks_per_cu = blocks_per_cu
@@ -212,6 +219,45 @@ class DeviceBatch:
         self.mo = dev(batch.module_offsets, np.int32)
         self.hits = SbtHits(self.n_events, self.n_hits, self.eo.data_ptr(), self.mo.data_ptr(),
                             self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr())
+
+
+def to_f16_aos(x, y, z) -> np.ndarray:
+    """Hit coordinates as binary16 (IEEE round to nearest even) in array-of-
+    structures form: [n, 4] uint16 bit patterns x, y, z, 0."""
+    n = int(np.asarray(x).shape[0])
+    out = np.zeros((n, 4), np.float16)
+    out[:, 0] = np.asarray(x, np.float32)
+    out[:, 1] = np.asarray(y, np.float32)
+    out[:, 2] = np.asarray(z, np.float32)
+    return out.view(np.uint16)
+
+
+class DeviceBatchF16:
+    """Device copy of a batch with binary16 array-of-structures coordinates
+    (the sbt_hits_f16 of a call); xyzw: a [n, 4] uint16 array from
+    to_f16_aos, or None to convert the batch's binary32 coordinates."""
+
+    def __init__(self, batch, xyzw=None, device="cuda"):
+        torch = _torch()
+        self.n_events = int(batch.event_offsets.shape[0] - 1)
+        self.n_hits = int(batch.event_offsets[-1]) if self.n_events > 0 else 0
+        self.n_modules = int(batch.module_z.shape[0])
+        self.module_z = np.asarray(batch.module_z, dtype=np.float32)
+        if xyzw is None:
+            xyzw = to_f16_aos(batch.x, batch.y, batch.z)
+        assert xyzw.shape == (self.n_hits, 4) and xyzw.dtype == np.uint16
+
+        def dev(a, dt):
+            t = torch.from_numpy(np.ascontiguousarray(a, dtype=dt))
+            if t.numel() == 0:
+                t = torch.zeros(1, dtype=t.dtype)
+            return t.to(device)
+        # int16 on the device (torch has no uint16 tensors); the bits are what count
+        self.xyzw = dev(xyzw.reshape(-1).view(np.int16), np.int16)
+        self.eo = dev(batch.event_offsets, np.int32)
+        self.mo = dev(batch.module_offsets, np.int32)
+        self.hits = SbtHitsF16(self.n_events, self.n_hits, self.eo.data_ptr(), self.mo.data_ptr(),
+                               self.xyzw.data_ptr())
 
 
 class DeviceTracks:
@@ -327,6 +373,13 @@ class Context:
         out = out or DeviceTracks(batch.n_events, batch.n_hits)
         _check(lib().sbt_reconstruct_batched(self.handle, ctypes.byref(batch.hits), ctypes.byref(out.tracks),
                                              _stream_handle(stream)), "sbt_reconstruct_batched")
+        return out
+
+    def reconstruct_f16(self, batch: DeviceBatchF16, out: Optional[DeviceTracks] = None,
+                        stream=None) -> DeviceTracks:
+        out = out or DeviceTracks(batch.n_events, batch.n_hits)
+        _check(lib().sbt_reconstruct_batched_f16(self.handle, ctypes.byref(batch.hits), ctypes.byref(out.tracks),
+                                                 _stream_handle(stream)), "sbt_reconstruct_batched_f16")
         return out
 
     def autotune(self, sample: DeviceBatch, reps: int = 3, stream=None, cache: bool = True):

@@ -61,3 +61,12 @@ def event_batch(x, y, z, mo, module_z):
     return synth.concat([dict(x=np.asarray(x, np.float32), y=np.asarray(y, np.float32),
                               z=np.asarray(z, np.float32), module_counts=np.diff(mo).astype(np.int64),
                               truth=np.full(len(x), -1, np.int32))], module_z)
+
+
+def rounded_to_f16(batch):
+    """The batch with its coordinates rounded to binary16 (numpy, IEEE round
+    to nearest even) and widened back to binary32: the values the
+    half-precision input form carries."""
+    import dataclasses
+    r = lambda a: np.asarray(a, np.float32).astype(np.float16).astype(np.float32)
+    return dataclasses.replace(batch, x=r(batch.x), y=r(batch.y), z=r(batch.z))

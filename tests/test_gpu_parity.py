@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from _util import event_batch, tiny_random_event
+from _util import event_batch, rounded_to_f16, tiny_random_event
 from paper_2207_03936_amd import sbt, synth
 
 pytestmark = pytest.mark.gpu
@@ -275,6 +275,63 @@ def test_full_mu7_6_batch_all_events():
         ctx.reconstruct(dev, out)
         got = out.to_host()
         _same(got, want, f"batched mu7.6 x1000 replay {rep}")
+    ctx.close()
+
+
+# ------------------------------------------------------------------ half-precision input
+
+def run_batched_f16(batch, tuning=None):
+    p = sbt.make_params(batch.module_z)
+    ctx = sbt.Context(p, max(batch.n_events, 1), max(batch.n_hits, 1), tuning)
+    out = ctx.reconstruct_f16(sbt.DeviceBatchF16(batch)).to_host()
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("config,n", [("tiny", 20), ("mu7.6", 40), ("mu1-25", 30), ("mu30", 6)])
+def test_f16_matches_oracle_on_rounded_inputs(config, n):
+    """Binary16 array-of-structures input: the oracle on the same values
+    widened to binary32 (numpy's IEEE rounding) defines the tracks."""
+    say(f"f16 {config} x{n}")
+    b = synth.make_batch(config, n)
+    want = oracle.reconstruct(rounded_to_f16(b))
+    got = run_batched_f16(b)
+    assert not got[3].any()
+    _same(got, want, f"f16 {config}")
+
+
+@pytest.mark.parametrize("tpe,cap", [(64, 0), (256, 448), (1024, 1536)])
+def test_f16_independent_of_launch_configuration(tpe, cap):
+    say(f"f16 tuning tpe={tpe} cap={cap}")
+    b = synth.make_batch("mu30", 4, first=11)
+    want = oracle.reconstruct(rounded_to_f16(b))
+    _same(run_batched_f16(b, sbt.make_tuning(tpe, 2, cap)), want, f"f16 tpe={tpe} cap={cap}")
+
+
+def test_f16_full_mu7_6_batch():
+    say("f16 full mu7.6 x1000")
+    b = synth.make_batch("mu7.6")
+    want = oracle.reconstruct(rounded_to_f16(b))
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    dev = sbt.DeviceBatchF16(b)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    for rep in range(2):
+        out.fill_(-1)
+        ctx.reconstruct_f16(dev, out)
+        _same(out.to_host(), want, f"f16 mu7.6 x1000 replay {rep}")
+    ctx.close()
+
+
+def test_f16_rejects_misaligned_coordinates():
+    b = synth.make_batch("tiny", 2)
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    dev = sbt.DeviceBatchF16(b)
+    dev.hits.xyzw = dev.xyzw.data_ptr() + 2
+    with pytest.raises(sbt.SbtError) as ei:
+        ctx.reconstruct_f16(dev)
+    assert ei.value.code == sbt.SBT_ERR_INVALID_ARG
     ctx.close()
 
 
