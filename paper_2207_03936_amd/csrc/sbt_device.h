@@ -395,7 +395,9 @@ __device__ __forceinline__ int lane_xor(int v, int m)
 // (hits per module slot).  The sort scratch (histogram, fill counters, the
 // 32-bit sort keys and per-hit bins of events with at most sortcap/2 hits)
 // aliases the tracking area, which is filled only after the sort.
-//   ring   4 slots x CAP sorted hits (16 B each)
+//   ring   4 slots x CAP sorted hits (16 B each): traversal index u in slot
+//          u mod 4; module t+1 is filled into the slot of t-3 while t is
+//          being resolved
 //   tab    coarse phi index of each slot: first position whose phi16 high
 //          byte is >= b, b = 0..256
 //   freel  unflagged positions of the seeding stage's doublet module
@@ -409,9 +411,10 @@ __device__ __forceinline__ int lane_xor(int v, int m)
 extern __shared__ __align__(16) char g_lds[];
 
 constexpr int kTab = 257;
+constexpr int kSlots = 4;   // ring slots: traversal indices t-2 .. t+1
 __host__ __device__ constexpr uint32_t a16(uint32_t v) { return (v + 15u) & ~15u; }
-__host__ __device__ constexpr uint32_t lay_tab(int cap) { return 64u * (uint32_t)cap; }
-__host__ __device__ constexpr uint32_t lay_freel(int cap) { return a16(lay_tab(cap) + 8u * kTab); }
+__host__ __device__ constexpr uint32_t lay_tab(int cap) { return 16u * kSlots * (uint32_t)cap; }
+__host__ __device__ constexpr uint32_t lay_freel(int cap) { return a16(lay_tab(cap) + 2u * kSlots * kTab); }
 __host__ __device__ constexpr uint32_t lay_freem(int cap) { return lay_freel(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_frank(int cap) { return lay_freem(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_al0(int cap) { return lay_frank(cap) + a16(2u * cap); }
@@ -474,7 +477,7 @@ struct Shared {
     int maxmod;          // hits of the event's largest module
     int ovf;             // an LDS list overflowed
     int scan[2 * (B / 64)];
-    int slot_n[4];       // hits of the module held by each ring slot
+    int slot_n[kSlots];  // hits of the module held by each ring slot
     uint8_t mtab[(SBT_MAX_EVENT_HITS + 64) / 64];   // module of every 64th hit (sort)
 };
 
@@ -714,7 +717,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
 // ---------------------------------------------------------------- module windows
 // An event whose modules all fit the LDS slots (and whose hit flags fit the
 // LDS bitmap) runs the LDS instantiation of the tracking stages: traversal
-// index u lives in ring slot u & 3 and every window access is an LDS access.
+// index u lives in ring slot u mod 4 and every window access is an LDS access.
 // Any other event runs the memory instantiation, which reads the sorted
 // hits in memory directly.  Both compute the same thing.
 struct Win {
@@ -751,7 +754,7 @@ __device__ __forceinline__ Win window(const Prm &P, const Shared<B> &S, const Ev
 {
     Win w;
     if (kLds) {
-        const int s = u & 3;
+        const int s = u % kSlots;
         w.n = uni(S.slot_n[s]);
         w.h = Lay<CAP>::ring(s);
         w.tab = Lay<CAP>::tab(s);
@@ -765,16 +768,6 @@ __device__ __forceinline__ Win window(const Prm &P, const Shared<B> &S, const Ev
     return w;
 }
 
-// registers holding one module on its way into the ring
-template <int B>
-struct RingStage {
-    static constexpr int PF = (512 + B - 1) / B;
-    float x[PF], y[PF], z[PF];
-    uint32_t qid[PF];
-    uint16_t qp[PF];
-    int hi_first, hi_last;   // high bytes of the first and last phi16 (kTab when empty)
-};
-
 // coarse-index entries owned by position i > 0 of a slot whose phi16 is q
 // (qp: phi16 of position i-1): every high byte b with high(qp) < b <=
 // high(q) starts at i.  The entries up to the first hit's high byte (0) and
@@ -785,67 +778,34 @@ __device__ __forceinline__ void tab_fill(uint16_t *tab, int i, uint16_t q, uint1
     for (int b = (qp >> 8) + 1; b <= (q >> 8); ++b) tab[b] = (uint16_t)i;
 }
 
-template <int B>
-__device__ __forceinline__ void ring_load(const Prm &P, const Ev &v, int u, const Shared<B> &S,
-                                          RingStage<B> &R)
-{
-    const int k = kmod(P, u);
-    const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
-    const Hit16 *src = v.hs() + g;
-    R.hi_first = kTab;
-    R.hi_last = kTab;
-    if (n > 0) {
-        R.hi_first = q_of(at(src, 0)) >> 8;
-        R.hi_last = q_of(at(src, n - 1)) >> 8;
-    }
-#pragma unroll
-    for (int j = 0; j < RingStage<B>::PF; ++j) {
-        const int i = (int)threadIdx.x + j * B;
-        if (i < n) {
-            const Hit16 h = at(src, i);
-            R.x[j] = h.x;
-            R.y[j] = h.y;
-            R.z[j] = h.z;
-            R.qid[j] = h.qid;
-            R.qp[j] = i > 0 ? q_of(at(src, i - 1)) : (uint16_t)0;
-        }
-    }
-}
-
+// Copies the sorted hits of traversal index u into its ring slot and builds
+// the slot's coarse index, on lanes [l0, B) of the workgroup.
 template <int B, int CAP>
-__device__ __forceinline__ void ring_store(const Prm &P, const Ev &v, int u, Shared<B> &S,
-                                           const RingStage<B> &R)
+__device__ __forceinline__ void ring_fill(const Prm &P, const Ev &v, int u, Shared<B> &S, int l0)
 {
+    const int lane = (int)threadIdx.x - l0, nl = B - l0;
+    if (lane < 0) return;
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
-    const int s = u & 3;
-    if (threadIdx.x == 0) S.slot_n[s] = n;
+    const int s = u % kSlots;
+    if (lane == 0) S.slot_n[s] = n;
     Hit16 *ring = Lay<CAP>::ring(s);
     uint16_t *tab = Lay<CAP>::tab(s);
     const Hit16 *src = v.hs() + g;
     // n == 0: every entry is 0
-    const int hi_first = uni(R.hi_first), hi_last = uni(R.hi_last);
-    for (int b = threadIdx.x; b < kTab; b += B) {
+    int hi_first = kTab, hi_last = kTab;
+    if (n > 0) {
+        hi_first = q_of(at(src, 0)) >> 8;
+        hi_last = q_of(at(src, n - 1)) >> 8;
+    }
+    for (int b = lane; b < kTab; b += nl) {
         if (b <= hi_first) tab[b] = 0;
         else if (b > hi_last) tab[b] = (uint16_t)n;
     }
-#pragma unroll
-    for (int j = 0; j < RingStage<B>::PF; ++j) {
-        const int i = (int)threadIdx.x + j * B;
-        if (i < n) {
-            Hit16 h;
-            h.x = R.x[j];
-            h.y = R.y[j];
-            h.z = R.z[j];
-            h.qid = R.qid[j];
-            ring[i] = h;
-            tab_fill(tab, i, (uint16_t)(R.qid[j] & 0xFFFFu), R.qp[j]);
-        }
-    }
-    for (int i = (int)threadIdx.x + RingStage<B>::PF * B; i < n; i += B) {
+    for (int i = lane; i < n; i += nl) {
         const Hit16 h = at(src, i);
         ring[i] = h;
-        tab_fill(tab, i, q_of(h), q_of(at(src, i - 1)));
+        tab_fill(tab, i, q_of(h), i > 0 ? q_of(at(src, i - 1)) : (uint16_t)0);
     }
 }
 
@@ -1337,12 +1297,8 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
         S.cnt[0] = 0; S.cnt[1] = 0; S.cnt[2] = 0; S.cnt[3] = 0;
         S.ovf = 0;
     }
-    RingStage<B> R;
     if (kLds)
-        for (int u = 0; u < 4 && u < M; ++u) {
-            ring_load<B>(P, v, u, S, R);
-            ring_store<B, CAP>(P, v, u, S, R);
-        }
+        for (int u = 0; u < 4 && u < M; ++u) ring_fill<B, CAP>(P, v, u, S, 0);
     __syncthreads();
     uint16_t *l0 = kLds ? Lay<CAP>::al(0) : v.list(kListAct0);
     uint16_t *l1 = kLds ? Lay<CAP>::al(1) : v.list(kListAct1);
@@ -1358,9 +1314,15 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
         uint16_t *act = par ? l1 : l0;
         uint16_t *nxt = par ? l0 : l1;
         const bool more = t + 1 < M;
-        if (kLds && more) ring_load<B>(fresh(PP), fresh(v), t + 1, S, R);
         stage_follow_resolve<B, kLds, CAP>(PP, v, t, S, own, act, n_act, nxt, &S.cnt[1 + (par ^ 1)]);
-        if (kLds && more) ring_store<B, CAP>(fresh(PP), fresh(v), t + 1, S, R);
+        if (kLds && more) {
+            // module t+1 into the slot of t-3 (unused from here on), on the
+            // waves the resolution leaves idle (the last wave at least)
+            const int last = n_act > 0 ? n_act - ((n_act - 1) / B) * B : 0;
+            int l0 = (last + 63) & ~63;
+            if (l0 > B - 64) l0 = B - 64;
+            ring_fill<B, CAP>(fresh(PP), fresh(v), t + 1, S, l0);
+        }
         __syncthreads();
         const int n_keep = uni(S.cnt[1 + (par ^ 1)]);
         if (threadIdx.x == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
