@@ -163,7 +163,8 @@ struct Slot {
 };
 
 // tracks of a completed slot: per event, track offsets rebased to the event
-// (events' lists laid end to end) and the hit ids
+// (events' lists laid end to end) and the hit ids.  Blocks are recycled
+// (their pages stay mapped and nothing is cleared); the vectors only grow.
 struct ResultBlock {
     std::vector<int32_t> tho;
     std::vector<int32_t> th;
@@ -187,6 +188,7 @@ struct sbt_server {
     int open_slot;           // index of the slot admitting events, or -1
     std::vector<std::shared_ptr<ResultBlock>> store;   // blocks of the results last returned
     std::deque<ReadyResult> ready;                      // completed, not yet returned
+    std::vector<std::shared_ptr<ResultBlock>> blocks;   // recycled result blocks
     std::unique_ptr<Pool> pool;
 };
 
@@ -352,11 +354,21 @@ void collect(sbt_server *srv, Slot &s)
 {
     const double t = now_us();
     const int32_t E = s.n_events;
-    auto block = std::make_shared<ResultBlock>();
+    // a block no result refers to any more, else a new one
+    std::shared_ptr<ResultBlock> block;
+    for (auto &b : srv->blocks)
+        if (b.use_count() == 1) {
+            block = b;
+            break;
+        }
+    if (!block) {
+        block = std::make_shared<ResultBlock>();
+        srv->blocks.push_back(block);
+    }
     const int32_t T = s.heto[E];
     const int32_t A = s.htho[T];
-    block->tho.resize((size_t)T + (size_t)E);
-    block->th.resize((size_t)A);
+    if (block->tho.size() < (size_t)T + (size_t)E) block->tho.resize((size_t)T + (size_t)E);
+    if (block->th.size() < (size_t)A) block->th.resize((size_t)A);
     const size_t base = srv->ready.size();
     srv->ready.resize(base + (size_t)E);
     srv->pool->run(E, [&](int i) {
