@@ -258,14 +258,17 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
 
 /* ---- serving ---------------------------------------------------------------------
  * Continuous batching of single events that arrive over time.  The server
- * keeps `n_slots` batches of device memory resident (inputs, workspace and
- * outputs, `slot_hits`/`slot_events` capacity each, all inside
- * `device_budget_bytes`), admits queued events into the open slot while it
- * has room, and launches a slot on its own stream as soon as its previous
- * launch is complete and either it is full or `max_wait_us` passed since its
- * oldest event was queued.  Several slots are in flight at once, so events
- * that arrive while others are on the GPU overlap with them.  Results of an
- * event are identical to reconstructing it alone.                        */
+ * keeps `n_slots` batches of device memory resident (inputs and workspace,
+ * `slot_hits`/`slot_events` capacity each, all inside `device_budget_bytes`),
+ * admits queued events into the open slot while it has room, and launches a
+ * slot on its own stream as soon as its previous launch is complete and
+ * either it is full or `max_wait_us` passed since its oldest event was
+ * queued.  Several slots are in flight at once, so events that arrive while
+ * others are on the GPU overlap with them.  The kernels write each event's
+ * tracks into pinned host memory owned by the server (about
+ * 5.4 * slot_hits bytes per block, n_slots + 1 blocks, more while the caller
+ * holds results across polls).  Results of an event are identical to
+ * reconstructing it alone.                                               */
 typedef struct sbt_server sbt_server;
 
 typedef struct sbt_server_config {

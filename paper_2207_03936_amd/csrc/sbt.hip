@@ -133,13 +133,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutAr
     int oh = block_excl_scan<kScanThreads>(sh, sw, 1, &th);
     for (int i = beg; i < end; ++i) {
         O.eto[i] = ot;
+        ws_evinfo(W)[i].out_t = ot;
         ws_evinfo(W)[i].out_h = oh;
         ot += ws_evinfo(W)[i].nt;
         oh += ws_evinfo(W)[i].nh;
     }
     if (threadIdx.x == 0) {
         O.eto[E] = tt;
-        if (tt <= H.n_hits / 3) O.tho[tt] = th;
+        if (O.tho && tt <= H.n_hits / 3) O.tho[tt] = th;
     }
 }
 
@@ -151,9 +152,27 @@ __global__ __launch_bounds__(kWriteThreads) void k_write(HitsArgs H, Work W, Out
         const int nt = ws_evinfo(W)[e].nt, nh = ws_evinfo(W)[e].nh;
         if (nt == 0) continue;
         const int hb = H.eo[e];
-        const int t0 = O.eto[e], p0 = ws_evinfo(W)[e].out_h;
+        const int t0 = ws_evinfo(W)[e].out_t, p0 = ws_evinfo(W)[e].out_h;
         for (int i = threadIdx.x; i < nt; i += kWriteThreads) O.tho[t0 + i] = p0 + ws_toff(W)[hb + i];
         for (int j = threadIdx.x; j < nh; j += kWriteThreads) O.th[p0 + j] = ws_sthits(W)[hb + j];
+    }
+}
+
+// Each event's tracks as a CSR of their own (offsets from zero), for callers
+// that hand out one event at a time.  Reads only the workspace, so the
+// outputs may live in host memory the device can write.
+__global__ __launch_bounds__(kWriteThreads) void k_write_events(HitsArgs H, Work W, EventOut O)
+{
+    for (int e = blockIdx.x; e < H.n_events; e += gridDim.x) {
+        const EvInfo I = ws_evinfo(W)[e];
+        if (threadIdx.x == 0) {
+            O.status[e] = I.st;
+            O.hoff[e] = I.out_h;
+        }
+        const int hb = H.eo[e];
+        int32_t *tho = O.tho + I.out_t + e;
+        for (int i = threadIdx.x; i <= I.nt; i += kWriteThreads) tho[i] = i < I.nt ? ws_toff(W)[hb + i] : I.nh;
+        for (int j = threadIdx.x; j < I.nh; j += kWriteThreads) O.th[I.out_h + j] = ws_sthits(W)[hb + j];
     }
 }
 
@@ -336,8 +355,8 @@ int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
     return SBT_OK;
 }
 
-int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W,
-                   const OutArgs &O, hipStream_t s, hipEvent_t *marks)
+// k_prepare and the persistent kernel: per-event track lists in the workspace
+int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W, hipStream_t s)
 {
     int grid = 0;
     int rc = persistent_grid(T, H.n_events, &grid);
@@ -350,10 +369,17 @@ int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, 
     HitsArgs Hc = H;
     Work Wc = W;
     void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap};
-    if (marks) HIP_TRY(hipEventRecord(marks[0], s));
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
     HIP_TRY(hipLaunchKernel(persistent_kernel(T.threads_per_event, cap), dim3(grid), dim3(T.threads_per_event), args,
                             lds, s));
+    return SBT_OK;
+}
+
+int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W,
+                   const OutArgs &O, hipStream_t s, hipEvent_t *marks)
+{
+    if (marks) HIP_TRY(hipEventRecord(marks[0], s));
+    if (int rc = launch_persistent(P, T, H, W, s)) return rc;
     if (marks) HIP_TRY(hipEventRecord(marks[1], s));
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, H, W, O);
     if (marks) HIP_TRY(hipEventRecord(marks[2], s));
@@ -777,6 +803,25 @@ int launch_batched_raw(const sbt_params &params, const sbt_tuning &tuning, const
     Work W;
     carve(H.n_events, H.n_hits, (char *)workspace, &W);
     return launch_batched(params, tuning, H, W, O, stream, nullptr);
+}
+
+int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
+                          const EventOut &out, void *workspace, hipStream_t stream)
+{
+    const HitsArgs H = hits_args(&hits);
+    if (H.n_events == 0) return SBT_ERR_INVALID_ARG;
+    Work W;
+    carve(H.n_events, H.n_hits, (char *)workspace, &W);
+    if (int rc = launch_persistent(params, tuning, H, W, stream)) return rc;
+    OutArgs O;
+    O.eto = out.eto;
+    O.tho = nullptr;
+    O.th = nullptr;
+    O.status = nullptr;
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, stream, H, W, O);
+    hipLaunchKernelGGL(k_write_events, dim3(std::min(H.n_events, 8192)), dim3(kWriteThreads), 0, stream, H, W,
+                       out);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
 }
 
 sbt_tuning default_tuning_config() { return default_tuning(); }

@@ -65,7 +65,8 @@ struct EvInfo {
     int32_t out_h;      // first output hit position (batch scan)
     int32_t st;         // SBT_EV_* status
     int32_t nfin;       // final records (plain form)
-    int32_t pad[3];
+    int32_t out_t;      // first output track position (batch scan)
+    int32_t pad[2];
 };
 
 // record flags

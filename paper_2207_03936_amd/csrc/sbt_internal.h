@@ -17,6 +17,21 @@ size_t workspace_bytes(int32_t E, int32_t H);
 int launch_batched_raw(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
                        const sbt_tracks &tracks, void *workspace, hipStream_t stream);
 
+// Per-event track lists, each a CSR of its own, for a batch of E events with
+// T accepted tracks in all.  Any memory the device can write (device or
+// pinned host memory).
+struct EventOut {
+    int32_t *eto;     // [E+1] the batch's track offsets per event
+    int32_t *status;  // [E]   event_status bits
+    int32_t *hoff;    // [E]   first position of event e's hits in th
+    int32_t *tho;     // [T+E] event e's offsets, from 0, at tho[eto[e]+e .. eto[e+1]+e]
+    int32_t *th;      // [sum of track lengths] hit ids, event by event
+};
+
+// The batched sequence writing per-event lists (E >= 1).
+int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
+                          const EventOut &out, void *workspace, hipStream_t stream);
+
 // The library's default launch configuration.
 sbt_tuning default_tuning_config();
 int tuning_valid(const sbt_tuning &t);

@@ -1,22 +1,25 @@
 // Serving loop: continuous batching of single events over resident device
 // slots (the C ABI in include/sbt.h, "serving").
 //
-// Each slot owns, for the server's lifetime, device inputs, workspace and
-// outputs for up to slot_events events / slot_hits hits, pinned host staging
-// for both directions, a stream (default priority) and a completion event.
-// Events queued by sbt_server_submit are packed into the slot that is open
-// for admission; a slot is launched (H2D copy, batched reconstruction, D2H
-// copy, completion event, all on its stream) when it cannot take the next
-// queued event, when its oldest event has waited max_wait_us, or at once when
-// no other slot is on the device.  While slots are in flight, newly arriving
-// events are admitted into free slots, so their work overlaps on the device.
-// An event's tracks depend only on its own hits, so a result is the same
-// whether the event ran alone or in a mix.
+// Each slot owns, for the server's lifetime, device inputs and workspace for
+// up to slot_events events / slot_hits hits, pinned host staging of the
+// inputs, a stream (default priority) and a completion event.  Events queued
+// by sbt_server_submit are packed into the slot that is open for admission; a
+// slot is launched (one H2D copy, batched reconstruction, completion event,
+// all on its stream) when it cannot take the next queued event, when its
+// oldest event has waited max_wait_us, or at once when no other slot is on
+// the device.  While slots are in flight, newly arriving events are admitted
+// into free slots, so their work overlaps on the device.  An event's tracks
+// depend only on its own hits, so a result is the same whether the event ran
+// alone or in a mix.
 //
-// Host work is spread over a small pool of threads owned by the server: the
-// hits of a slot's events are copied into its pinned staging when the slot
-// launches, and a completed slot's tracks are rebased per event into one
-// result block, both in parallel over events.
+// The reconstruction writes each event's tracks, as a CSR of its own, straight
+// into a pinned host result block that the returned results point into; blocks
+// are recycled once no result refers to them.  No copy engine runs after the
+// kernels, so a slot's H2D copy never queues behind another slot's output
+// copy waiting for its kernels, and the host does not copy results.  The hits
+// of a slot's events are copied into its pinned staging at launch by a small
+// pool of threads owned by the server, in parallel over events.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -141,33 +144,32 @@ private:
 
 enum SlotState { kFree = 0, kOpen = 1, kInFlight = 2 };
 
+// Tracks of one launch, in pinned host memory the device writes: per event
+// its status, track count (eto), offsets from zero and hit ids.
+struct ResultBlock {
+    char *mem = nullptr;
+    int32_t *eto = nullptr, *st = nullptr, *hoff = nullptr, *tho = nullptr, *th = nullptr;
+    ~ResultBlock()
+    {
+        if (mem) (void)hipHostFree(mem);
+    }
+};
+
 struct Slot {
-    // device
+    // device inputs (event and module offsets, then x, y, z packed for the
+    // launch's hit count) and workspace
     char *dmem = nullptr;
-    float *dx = nullptr, *dy = nullptr, *dz = nullptr;
-    int32_t *deo = nullptr, *dmo = nullptr;
-    int32_t *deto = nullptr, *dtho = nullptr, *dth = nullptr, *dst = nullptr;
     void *dwork = nullptr;
-    // pinned host, same layout as the device inputs / outputs
+    // pinned host staging, same layout as the device inputs
     char *hin = nullptr;
-    float *hx = nullptr, *hy = nullptr, *hz = nullptr;
     int32_t *heo = nullptr, *hmo = nullptr;
-    char *hout = nullptr;
-    int32_t *heto = nullptr, *htho = nullptr, *hth = nullptr, *hst = nullptr;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     SlotState state = kFree;
     int32_t n_events = 0, n_hits = 0;
     double t_oldest = 0.0;
     std::vector<SlotEvent> events;
-};
-
-// tracks of a completed slot: per event, track offsets rebased to the event
-// (events' lists laid end to end) and the hit ids.  Blocks are recycled
-// (their pages stay mapped and nothing is cleared); the vectors only grow.
-struct ResultBlock {
-    std::vector<int32_t> tho;
-    std::vector<int32_t> th;
+    std::shared_ptr<ResultBlock> block;   // written by the launch in flight
 };
 
 struct ReadyResult {
@@ -188,18 +190,18 @@ struct sbt_server {
     int open_slot;           // index of the slot admitting events, or -1
     std::vector<std::shared_ptr<ResultBlock>> store;   // blocks of the results last returned
     std::deque<ReadyResult> ready;                      // completed, not yet returned
-    std::vector<std::shared_ptr<ResultBlock>> blocks;   // recycled result blocks
+    std::vector<std::shared_ptr<ResultBlock>> blocks;   // every result block (recycled)
     std::unique_ptr<Pool> pool;
 };
 
 namespace {
 
-// byte layout of one slot
+// byte layout of one slot's inputs (the same on the device and in the pinned
+// staging) and of a result block
 struct SlotLayout {
-    size_t x, y, z, eo, mo, in_total;      // inputs
-    size_t eto, tho, th, st, out_total;    // outputs
-    size_t work;
-    size_t device_total;
+    size_t eo, mo, xyz, in_total;                  // inputs: x, y, z from xyz on
+    size_t work, device_total;
+    size_t r_eto, r_st, r_hoff, r_tho, r_th, r_total;   // result block
 };
 
 SlotLayout slot_layout(const sbt_server_config &c, int M)
@@ -207,22 +209,24 @@ SlotLayout slot_layout(const sbt_server_config &c, int M)
     SlotLayout L;
     const size_t H = (size_t)c.slot_hits, E = (size_t)c.slot_events;
     size_t o = 0;
-    L.x = o; o += align_up(4 * H);
-    L.y = o; o += align_up(4 * H);
-    L.z = o; o += align_up(4 * H);
     L.eo = o; o += align_up(4 * (E + 1));
     L.mo = o; o += align_up(4 * (E * M + 1));
+    L.xyz = o; o += 3 * align_up(4 * H);
     L.in_total = o;
-    size_t p = 0;
-    L.eto = p; p += align_up(4 * (E + 1));
-    L.tho = p; p += align_up(4 * (H / 3 + 1));
-    L.th = p; p += align_up(4 * H);
-    L.st = p; p += align_up(4 * E);
-    L.out_total = p;
     L.work = align_up(sbt::workspace_bytes(c.slot_events, c.slot_hits));
-    L.device_total = L.in_total + L.out_total + L.work;
+    L.device_total = L.in_total + L.work;
+    size_t r = 0;
+    L.r_eto = r; r += align_up(4 * (E + 1));
+    L.r_st = r; r += align_up(4 * E);
+    L.r_hoff = r; r += align_up(4 * E);
+    L.r_tho = r; r += align_up(4 * (H / 3 + E + 1));   // tracks have >= 3 distinct hits
+    L.r_th = r; r += align_up(4 * H);
+    L.r_total = r;
     return L;
 }
+
+// bytes from one of x, y, z to the next for a launch of H hits
+size_t xyz_stride(size_t H) { return align_up(4 * H); }
 
 void free_slot(Slot &s)
 {
@@ -230,7 +234,6 @@ void free_slot(Slot &s)
     if (s.stream) (void)hipStreamDestroy(s.stream);
     if (s.dmem) (void)hipFree(s.dmem);
     if (s.hin) (void)hipHostFree(s.hin);
-    if (s.hout) (void)hipHostFree(s.hout);
     s = Slot();
 }
 
@@ -238,32 +241,35 @@ int init_slot(Slot &s, const SlotLayout &L)
 {
     if (hipMalloc(&s.dmem, L.device_total) != hipSuccess) return SBT_ERR_NOMEM;
     if (hipHostMalloc(&s.hin, L.in_total, hipHostMallocDefault) != hipSuccess) return SBT_ERR_NOMEM;
-    if (hipHostMalloc(&s.hout, L.out_total, hipHostMallocDefault) != hipSuccess) return SBT_ERR_NOMEM;
     if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess) return SBT_ERR_HIP;
     if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) return SBT_ERR_HIP;
-    char *d = s.dmem;
-    s.dx = (float *)(d + L.x);
-    s.dy = (float *)(d + L.y);
-    s.dz = (float *)(d + L.z);
-    s.deo = (int32_t *)(d + L.eo);
-    s.dmo = (int32_t *)(d + L.mo);
-    char *dout = d + L.in_total;
-    s.deto = (int32_t *)(dout + L.eto);
-    s.dtho = (int32_t *)(dout + L.tho);
-    s.dth = (int32_t *)(dout + L.th);
-    s.dst = (int32_t *)(dout + L.st);
-    s.dwork = d + L.in_total + L.out_total;
-    s.hx = (float *)(s.hin + L.x);
-    s.hy = (float *)(s.hin + L.y);
-    s.hz = (float *)(s.hin + L.z);
+    s.dwork = s.dmem + L.in_total;
     s.heo = (int32_t *)(s.hin + L.eo);
     s.hmo = (int32_t *)(s.hin + L.mo);
-    s.heto = (int32_t *)(s.hout + L.eto);
-    s.htho = (int32_t *)(s.hout + L.tho);
-    s.hth = (int32_t *)(s.hout + L.th);
-    s.hst = (int32_t *)(s.hout + L.st);
     s.state = kFree;
     return SBT_OK;
+}
+
+std::shared_ptr<ResultBlock> new_block(const SlotLayout &L)
+{
+    std::shared_ptr<ResultBlock> b(new (std::nothrow) ResultBlock());
+    if (!b || hipHostMalloc(&b->mem, L.r_total, hipHostMallocDefault) != hipSuccess) return nullptr;
+    b->eto = (int32_t *)(b->mem + L.r_eto);
+    b->st = (int32_t *)(b->mem + L.r_st);
+    b->hoff = (int32_t *)(b->mem + L.r_hoff);
+    b->tho = (int32_t *)(b->mem + L.r_tho);
+    b->th = (int32_t *)(b->mem + L.r_th);
+    return b;
+}
+
+// a block no slot or result refers to any more, else a new one
+std::shared_ptr<ResultBlock> free_block(sbt_server *srv, const SlotLayout &L)
+{
+    for (auto &b : srv->blocks)
+        if (b.use_count() == 1) return b;
+    std::shared_ptr<ResultBlock> b = new_block(L);
+    if (b) srv->blocks.push_back(b);
+    return b;
 }
 
 // Admits a queued event into an open slot: offsets now, hits at launch.
@@ -303,92 +309,70 @@ int launch(sbt_server *srv, Slot &s)
     const int M = srv->params.n_modules;
     const SlotLayout L = slot_layout(srv->cfg, M);
     const size_t E = (size_t)s.n_events, H = (size_t)s.n_hits;
+    const size_t stride = xyz_stride(H);
     hipStream_t st = s.stream;
-    // hits into the pinned staging, in parallel over events
+    std::shared_ptr<ResultBlock> block = free_block(srv, L);
+    if (!block) return SBT_ERR_NOMEM;
+    // hits into the pinned staging, x, y, z packed for this launch, in parallel over events
+    float *hx = (float *)(s.hin + L.xyz), *hy = (float *)(s.hin + L.xyz + stride),
+          *hz = (float *)(s.hin + L.xyz + 2 * stride);
     srv->pool->run((int)s.events.size(), [&](int i) {
         SlotEvent &ev = s.events[(size_t)i];
         if (ev.n > 0) {
-            memcpy(s.hx + ev.base, ev.x, sizeof(float) * ev.n);
-            memcpy(s.hy + ev.base, ev.y, sizeof(float) * ev.n);
-            memcpy(s.hz + ev.base, ev.z, sizeof(float) * ev.n);
+            memcpy(hx + ev.base, ev.x, sizeof(float) * ev.n);
+            memcpy(hy + ev.base, ev.y, sizeof(float) * ev.n);
+            memcpy(hz + ev.base, ev.z, sizeof(float) * ev.n);
         }
         std::vector<float>().swap(ev.own);
     });
-    // inputs (only the used prefix of each array)
-    if (H > 0) {
-        if (hipMemcpyAsync(s.dx, s.hx, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
-        if (hipMemcpyAsync(s.dy, s.hy, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
-        if (hipMemcpyAsync(s.dz, s.hz, 4 * H, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
-    }
-    if (hipMemcpyAsync(s.deo, s.heo, 4 * (E + 1), hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
-    if (hipMemcpyAsync(s.dmo, s.hmo, 4 * (E * M + 1), hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
+    // offsets and hits in one copy
+    if (hipMemcpyAsync(s.dmem, s.hin, L.xyz + 3 * stride, hipMemcpyHostToDevice, st) != hipSuccess)
+        return SBT_ERR_HIP;
     sbt_hits hits;
     hits.n_events = (int32_t)E;
     hits.n_hits = (int32_t)H;
-    hits.event_offsets = s.deo;
-    hits.module_offsets = s.dmo;
-    hits.x = s.dx;
-    hits.y = s.dy;
-    hits.z = s.dz;
-    sbt_tracks tr;
-    tr.event_track_offsets = s.deto;
-    tr.track_hit_offsets = s.dtho;
-    tr.track_hits = s.dth;
-    tr.event_status = s.dst;
-    int rc = sbt::launch_batched_raw(srv->params, srv->tuning, hits, tr, s.dwork, st);
+    hits.event_offsets = (const int32_t *)(s.dmem + L.eo);
+    hits.module_offsets = (const int32_t *)(s.dmem + L.mo);
+    hits.x = (const float *)(s.dmem + L.xyz);
+    hits.y = (const float *)(s.dmem + L.xyz + stride);
+    hits.z = (const float *)(s.dmem + L.xyz + 2 * stride);
+    sbt::EventOut out;
+    out.eto = block->eto;
+    out.status = block->st;
+    out.hoff = block->hoff;
+    out.tho = block->tho;
+    out.th = block->th;
+    int rc = sbt::launch_batched_events(srv->params, srv->tuning, hits, out, s.dwork, st);
     if (rc) return rc;
-    // outputs: capacities follow from the input size (tracks are disjoint, >= 3 hits)
-    if (hipMemcpyAsync(s.heto, s.deto, 4 * (E + 1), hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
-    if (hipMemcpyAsync(s.htho, s.dtho, 4 * (H / 3 + 1), hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
-    if (H > 0 && hipMemcpyAsync(s.hth, s.dth, 4 * H, hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
-    if (hipMemcpyAsync(s.hst, s.dst, 4 * E, hipMemcpyDeviceToHost, st) != hipSuccess) return SBT_ERR_HIP;
     if (hipEventRecord(s.done, st) != hipSuccess) return SBT_ERR_HIP;
-    (void)L;
+    s.block = std::move(block);
     s.state = kInFlight;
     return SBT_OK;
 }
 
-// Moves a completed slot's events to the ready queue: one result block, filled
-// in parallel over events.
+// Moves a completed slot's events to the ready queue; their results point
+// into the slot's result block.
 void collect(sbt_server *srv, Slot &s)
 {
     const double t = now_us();
     const int32_t E = s.n_events;
-    // a block no result refers to any more, else a new one
-    std::shared_ptr<ResultBlock> block;
-    for (auto &b : srv->blocks)
-        if (b.use_count() == 1) {
-            block = b;
-            break;
-        }
-    if (!block) {
-        block = std::make_shared<ResultBlock>();
-        srv->blocks.push_back(block);
-    }
-    const int32_t T = s.heto[E];
-    const int32_t A = s.htho[T];
-    if (block->tho.size() < (size_t)T + (size_t)E) block->tho.resize((size_t)T + (size_t)E);
-    if (block->th.size() < (size_t)A) block->th.resize((size_t)A);
-    const size_t base = srv->ready.size();
-    srv->ready.resize(base + (size_t)E);
-    srv->pool->run(E, [&](int i) {
-        const int32_t t0 = s.heto[i], t1 = s.heto[i + 1];
-        const int32_t h0 = s.htho[t0], h1 = s.htho[t1];
-        int32_t *tho = block->tho.data() + t0 + i;
-        for (int32_t k = t0; k <= t1; ++k) tho[k - t0] = s.htho[k] - h0;
-        if (h1 > h0) memcpy(block->th.data() + h0, s.hth + h0, sizeof(int32_t) * (size_t)(h1 - h0));
-        ReadyResult &rr = srv->ready[base + (size_t)i];
+    const ResultBlock &b = *s.block;
+    for (int32_t i = 0; i < E; ++i) {
+        ReadyResult rr;
+        const int32_t t0 = b.eto[i], t1 = b.eto[i + 1];
         rr.r.request_id = s.events[(size_t)i].id;
-        rr.r.status = s.hst[i];
+        rr.r.status = b.st[i];
         rr.r.n_tracks = t1 - t0;
         rr.r.track_hit_offsets = nullptr;
         rr.r.track_hits = nullptr;
         rr.r.t_submit_us = s.events[(size_t)i].t_submit;
         rr.r.t_done_us = t;
+        rr.block = s.block;
         rr.tho_at = (size_t)t0 + (size_t)i;
-        rr.th_at = (size_t)h0;
-    });
-    for (int32_t i = 0; i < E; ++i) srv->ready[base + (size_t)i].block = block;
+        rr.th_at = (size_t)b.hoff[i];
+        srv->ready.push_back(std::move(rr));
+    }
+    s.block.reset();
     s.events.clear();
     s.n_events = 0;
     s.n_hits = 0;
@@ -485,6 +469,17 @@ int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const 
             return rc;
         }
     }
+    // one result block per slot and one for the results last returned; more
+    // are added while callers hold results longer
+    for (int i = 0; i <= c.n_slots; ++i) {
+        std::shared_ptr<ResultBlock> b = new_block(L);
+        if (!b) {
+            for (auto &x : srv->slots) free_slot(x);
+            delete srv;
+            return SBT_ERR_NOMEM;
+        }
+        srv->blocks.push_back(std::move(b));
+    }
     *out = srv;
     return SBT_OK;
 }
@@ -540,8 +535,8 @@ int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_res
     while (n < max_results && !srv->ready.empty()) {
         ReadyResult &rr = srv->ready.front();
         results[n] = rr.r;
-        results[n].track_hit_offsets = rr.block->tho.data() + rr.tho_at;
-        results[n].track_hits = rr.block->th.data() + rr.th_at;
+        results[n].track_hit_offsets = rr.block->tho + rr.tho_at;
+        results[n].track_hits = rr.block->th + rr.th_at;
         if (srv->store.empty() || srv->store.back() != rr.block) srv->store.push_back(rr.block);
         srv->ready.pop_front();
         ++n;
