@@ -103,12 +103,16 @@ def copy_bandwidth(torch, mib=1024, reps=10):
     return 2 * 4 * n / sec / 1e9
 
 
-def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False):
+def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False, streams=None, d2h=False):
     """Whole-batch rate with the hits in pinned host memory at the start and
-    the tracks back in pinned host memory at the end.  Sequential: H2D,
-    reconstruction and D2H on one stream.  Pipelined: two contexts on two
-    streams, so the copies of one batch overlap the reconstruction of the
-    other."""
+    the tracks in pinned host memory at the end: H2D copies of the inputs,
+    then the reconstruction, whose kernels write the tracks straight into
+    pinned host buffers (no D2H copy queues in the copy engine behind them).
+    Sequential: everything on one stream.  Pipelined: two contexts on two
+    streams, so the input copy of one batch overlaps the reconstruction of the
+    other.  The two streams should be the same for every pipelined leg: HIP
+    maps streams onto a few hardware queues (four by default), and streams
+    that share one run their work in a single order."""
     def pinned(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
     heo, hmo = pinned(batch.event_offsets, np.int32), pinned(batch.module_offsets, np.int32)
@@ -128,28 +132,31 @@ def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False):
         coords = lambda dev: [dev.x, dev.y, dev.z]
         run = lambda c, dev, out, st: c.reconstruct(dev, out, st)
         coord_bytes = 12 * H
-    outs = [sbt.DeviceTracks(E, H) for _ in range(lanes)]
-    streams = [torch.cuda.Stream() for _ in range(lanes)] if pipelined else [torch.cuda.current_stream()]
-    run(ctxs[0], devs[0], outs[0], torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    T = int(outs[0].eto[-1].item())
-    A = int(outs[0].tho[T].item())
-    hout = [(torch.empty(E + 1, dtype=torch.int32).pin_memory(), torch.empty(T + 1, dtype=torch.int32).pin_memory(),
-             torch.empty(max(A, 1), dtype=torch.int32).pin_memory()) for _ in range(lanes)]
+    outs = [sbt.DeviceTracks(E, H, pinned=not d2h) for _ in range(lanes)]
+    if d2h:
+        hout = [sbt.DeviceTracks(E, H, pinned=True) for _ in range(lanes)]
+    if not pipelined:
+        streams = [torch.cuda.current_stream()]
+    elif streams is None:
+        streams = [torch.cuda.Stream() for _ in range(lanes)]
 
     def step(k):
         i = k % lanes
-        dev, out, (oeto, otho, oth), st = devs[i], outs[i], hout[i], streams[i]
+        dev, out, st = devs[i], outs[i], streams[i]
         with torch.cuda.stream(st):
             for d, h in list(zip(coords(dev), hcoords)) + [(dev.eo, heo), (dev.mo, hmo)]:
                 d.copy_(h, non_blocking=True)
             run(ctxs[i], dev, out, st)
-            oeto.copy_(out.eto, non_blocking=True)
-            otho.copy_(out.tho[:T + 1], non_blocking=True)
-            oth[:A].copy_(out.th[:A], non_blocking=True)
+            if d2h:
+                for a in ("eto", "tho", "th", "status"):
+                    getattr(hout[i], a).copy_(getattr(out, a), non_blocking=True)
     for k in range(2 * lanes):
         step(k)
     torch.cuda.synchronize()
+    T = int(outs[0].eto[-1])
+    A = int(outs[0].tho[T])
+    if d2h:
+        T, A = int(hout[0].eto[-1]), int(hout[0].tho[T])
     t0 = time.perf_counter()
     for k in range(steps):
         step(k)
@@ -158,12 +165,12 @@ def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False):
     for c in ctxs:
         c.close()
     in_bytes = coord_bytes + 4 * (E + 1) + 4 * batch.module_offsets.shape[0]
-    out_bytes = 4 * (E + 1) + 4 * (T + 1) + 4 * A
+    out_bytes = 4 * (E + 1) + 4 * (T + 1) + 4 * A + 4 * E
     return dict(events_per_s=round(E / sec, 1), ms_per_step=round(sec * 1e3, 4),
                 pcie_bytes_per_step=int(in_bytes + out_bytes),
-                note=("two contexts on two streams: copies of one batch overlap the reconstruction of the other"
-                      if pipelined else "H2D, reconstruction and D2H on one stream") +
-                     "; hits in pinned host memory before, tracks in pinned host memory after")
+                note=("two contexts on two streams: the input copy of one batch overlaps the reconstruction of "
+                      "the other" if pipelined else "H2D copy and reconstruction on one stream") +
+                     "; hits in pinned host memory before, tracks written by the kernels into pinned host memory")
 
 
 def _oracle_slice(args):
@@ -334,13 +341,16 @@ def main():
     copy_gbps = copy_bandwidth(torch)
     sq = measured_sq(H)
     e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
-    e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True)
+    pipe_streams = [torch.cuda.Stream() for _ in range(2)]
+    e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
+                       streams=pipe_streams)
     # half-precision array-of-structures input (the paper's hit-storage optimisation)
     dev16 = sbt.DeviceBatchF16(batch)
     out16 = sbt.DeviceTracks(E, H)
     sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16), args.steps, args.warmup)
     got16 = out16.to_host()
-    e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True)
+    e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
+                         streams=pipe_streams)
     del dev16, out16
 
     result = {

@@ -148,8 +148,9 @@ typedef struct sbt_hits_f16 {
     const uint16_t *xyzw;
 } sbt_hits_f16;
 
-/* Output (device pointers), CSR over events and tracks.  Capacities follow
- * from the method: tracks are disjoint and have >= 3 hits.
+/* Output, CSR over events and tracks: device memory, or pinned host memory
+ * (hipHostMalloc) that the kernels write directly; they never read it back.
+ * Capacities follow from the method: tracks are disjoint and have >= 3 hits.
  * event_track_offsets [n_events+1]: tracks of event e are
  *                 [event_track_offsets[e], event_track_offsets[e+1]).
  * track_hit_offsets   [n_hits/3 + 1]: hits of track t are

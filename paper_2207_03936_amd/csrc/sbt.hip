@@ -82,7 +82,7 @@ __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
 // Resets the work counter and orders the events by size, largest first, so
 // the persistent workgroups start the longest events early (the order of
 // processing never changes an event's result).  Counting sort on N / 64.
-constexpr int kOrderThreads = 1024;
+constexpr int kOrderThreads = 256;    // small, so it fits beside another stream's persistent workgroups
 constexpr int kOrderClasses = 1024;
 __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 {
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 // shared tail -----------------------------------------------------------------
 
 // exclusive scan over events of the per-event track and hit counts
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;     // small, so it fits beside another stream's persistent workgroups
 __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutArgs O)
 {
     const int E = H.n_events;

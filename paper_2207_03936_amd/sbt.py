@@ -261,15 +261,18 @@ class DeviceBatchF16:
 
 
 class DeviceTracks:
-    """Output buffers sized for a batch: the sbt_tracks of a call."""
+    """Output buffers sized for a batch: the sbt_tracks of a call.  With
+    pinned=True they are pinned host memory that the kernels write directly
+    (read them after synchronising the stream of the call)."""
 
-    def __init__(self, n_events, n_hits, device="cuda"):
+    def __init__(self, n_events, n_hits, device="cuda", pinned=False):
         torch = _torch()
         self.n_events, self.n_hits = int(n_events), int(n_hits)
-        self.eto = torch.zeros(self.n_events + 1, dtype=torch.int32, device=device)
-        self.tho = torch.zeros(self.n_hits // 3 + 1, dtype=torch.int32, device=device)
-        self.th = torch.zeros(max(self.n_hits, 1), dtype=torch.int32, device=device)
-        self.status = torch.zeros(max(self.n_events, 1), dtype=torch.int32, device=device)
+        kw = dict(dtype=torch.int32, pin_memory=True) if pinned else dict(dtype=torch.int32, device=device)
+        self.eto = torch.zeros(self.n_events + 1, **kw)
+        self.tho = torch.zeros(self.n_hits // 3 + 1, **kw)
+        self.th = torch.zeros(max(self.n_hits, 1), **kw)
+        self.status = torch.zeros(max(self.n_events, 1), **kw)
         self.tracks = SbtTracks(self.eto.data_ptr(), self.tho.data_ptr(), self.th.data_ptr(),
                                 self.status.data_ptr())
 

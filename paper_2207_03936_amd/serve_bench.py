@@ -25,7 +25,7 @@ import numpy as np
 from . import sbt, synth
 
 
-def make_server(params, budget_bytes=8 << 30, n_slots=4, slot_events=512, slot_hits=1 << 21, max_wait_us=300,
+def make_server(params, budget_bytes=8 << 30, n_slots=4, slot_events=512, slot_hits=3 << 20, max_wait_us=300,
                 tuning=None):
     return sbt.Server(params, device_budget_bytes=budget_bytes, n_slots=n_slots, slot_events=slot_events,
                       slot_hits=slot_hits, max_wait_us=max_wait_us, tuning=tuning)

@@ -359,3 +359,31 @@ def test_repeat_runs_identical():
     for i in range(19):
         _same(ctx.reconstruct(dev).to_host(), first[:3], f"repeat {i}")
     ctx.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "batched", "f16"])
+def test_outputs_in_pinned_host_memory(form):
+    """Tracks written by the kernels straight into pinned host buffers equal
+    the oracle's (the kernels only write the outputs, never read them)."""
+    import torch
+    say(f"pinned host outputs, {form}")
+    b = synth.make_batch("mu1-25", 24)
+    p = sbt.make_params(b.module_z)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits, pinned=True).fill_(-7)
+    if form == "plain":
+        sbt.sbt_reconstruct(p, sbt.DeviceBatch(b), out)
+        want = oracle.reconstruct(b)
+    else:
+        ctx = sbt.Context(p, b.n_events, b.n_hits)
+        if form == "batched":
+            ctx.reconstruct(sbt.DeviceBatch(b), out)
+            want = oracle.reconstruct(b)
+        else:
+            ctx.reconstruct_f16(sbt.DeviceBatchF16(b), out)
+            want = oracle.reconstruct(rounded_to_f16(b))
+        torch.cuda.synchronize()
+        ctx.close()
+    torch.cuda.synchronize()
+    got = out.to_host()
+    _same(got, want, f"pinned {form}")
+    assert not got[3].any()
