@@ -269,6 +269,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end legs (kernel profiles)")
     ap.add_argument("--tpe", type=int, default=0, help="threads per event (0: autotune)")
     ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (0: autotune)")
     ap.add_argument("--cap", type=int, default=672, help="LDS slot capacity in hits (with --tpe/--bpc)")
@@ -340,17 +341,19 @@ def main():
     traffic = measured_traffic(H)
     copy_gbps = copy_bandwidth(torch)
     sq = measured_sq(H)
-    e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
-    pipe_streams = [torch.cuda.Stream() for _ in range(2)]
-    e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
-                       streams=pipe_streams)
+    if not args.no_e2e:
+        e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
+        pipe_streams = [torch.cuda.Stream() for _ in range(2)]
+        e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
+                           streams=pipe_streams)
     # half-precision array-of-structures input (the paper's hit-storage optimisation)
     dev16 = sbt.DeviceBatchF16(batch)
     out16 = sbt.DeviceTracks(E, H)
     sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16), args.steps, args.warmup)
     got16 = out16.to_host()
-    e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
-                         streams=pipe_streams)
+    if not args.no_e2e:
+        e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
+                             streams=pipe_streams)
     del dev16, out16
 
     result = {
@@ -393,13 +396,15 @@ def main():
                           "valu_instructions_per_launch": int(sq["SQ_INSTS_VALU"]),
                           "salu_instructions_per_launch": int(sq["SQ_INSTS_SALU"]),
                           "lds_instructions_per_launch": int(sq["SQ_INSTS_LDS"])}
-    result["end_to_end"] = e2e
-    result["end_to_end_pipelined"] = e2e_p
+    if not args.no_e2e:
+        result["end_to_end"] = e2e
+        result["end_to_end_pipelined"] = e2e_p
     result["f16_aos"] = {"events_per_s": round(E / sec_f16, 1), "ms_per_step": round(sec_f16 * 1e3, 4),
                          "input_bytes_per_hit": 8, "n_tracks": int(got16[0][-1]),
-                         "end_to_end_pipelined": e2e_f16,
                          "note": "binary16 x, y, z, unused per hit, widened exactly on load; tracks equal the "
                                  "binary32 path on the rounded coordinates (GPU parity tests)"}
+    if not args.no_e2e:
+        result["f16_aos"]["end_to_end_pipelined"] = e2e_f16
     if tuned_ms is not None:
         result["autotune_ms"] = round(tuned_ms, 4)
     if not args.no_serve:
