@@ -68,6 +68,7 @@ extern "C" {
 #define SBT_EV_TOO_LARGE 1u   /* more than 65,535 hits: no tracks written           */
 #define SBT_EV_BAD_OFFSETS 2u /* offsets inconsistent or out of range: no tracks    */
 #define SBT_EV_INTERNAL 4u    /* internal consistency check failed (never expected) */
+#define SBT_EV_CUT 8u         /* rejected by the global event cut: no tracks written */
 
 /* Physics and geometry parameters.  They change results; the oracle takes the
  * same values.  Defaults used by the tests and benchmark are in parentheses.
@@ -101,6 +102,12 @@ extern "C" {
  *                 modules a forming track may skip in a row and still be
  *                 followed (Section 3: "allowed for tracks to miss a
  *                 module").  >= 0.  (1)
+ * max_event_hits  global event cut (Section 4, the first step of the paper's
+ *                 sequence, which drops the most densely populated events):
+ *                 an event with more hits is not reconstructed, gets status
+ *                 SBT_EV_CUT and no tracks.  0: no cut.  >= 0.  (0)
+ *                 sbt_gec_threshold computes the value that rejects a given
+ *                 fraction of a sample.
  */
 typedef struct sbt_params {
     int32_t n_modules;
@@ -113,6 +120,7 @@ typedef struct sbt_params {
     float max_scatter_forwarding;
     float max_tracklet_chi2;
     int32_t max_consecutive_misses;
+    int32_t max_event_hits;
 } sbt_params;
 
 /* Input batch (device pointers).
@@ -256,6 +264,35 @@ int sbt_context_stage_ms(sbt_context *ctx, float *stage_ms, int32_t n);
 int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted,
                        uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
                        void *stream);
+
+/* ---- the steps around Search by triplet in the paper's sequence (Section 4) ----------
+ *
+ * Global event cut: the threshold on the hit count that rejects at most
+ * floor(fraction * n_events) of the events, the most densely populated ones.
+ * It is the smallest count c, among 0 and the event sizes, that at most that
+ * many events exceed; events tied at c are kept.  event_offsets is a HOST
+ * array of n_events+1 entries.  fraction in [0, 1].  Put the result in
+ * sbt_params.max_event_hits.  Returns SBT_OK or SBT_ERR_INVALID_ARG.      */
+int sbt_gec_threshold(int32_t n_events, const int32_t *event_offsets, double fraction, int32_t *max_hits);
+
+/* Consolidation: the track data packed for the algorithms that follow.  For
+ * every track of `tracks` (device arrays, as sbt_reconstruct* wrote them):
+ *   hit_x/hit_y/hit_z [sum of track lengths]: the coordinates of track_hits,
+ *                 in the same order (copies of the input values);
+ *   state [6 * n_tracks]: per track x, y, z (the mean of its hits), tx, ty
+ *                 (dx/dz, dy/dz) and chi2 / (2n - 4), from an unweighted
+ *                 least-squares fit of x and y against z over its n hits.
+ * The fit is binary32: means first, then sums centred on the means, each
+ * accumulated in track order.  Capacities: n_hits floats for each hit_*
+ * array and 6 * (n_hits / 3) for state.  Device pointers, or pinned host
+ * memory the kernels write.  Asynchronous on `stream`.  `hits` must be the
+ * batch the tracks came from.  Returns SBT_OK, SBT_ERR_INVALID_ARG or SBT_ERR_HIP. */
+typedef struct sbt_track_states {
+    float *hit_x, *hit_y, *hit_z;
+    float *state;
+} sbt_track_states;
+
+int sbt_consolidate(const sbt_hits *hits, const sbt_tracks *tracks, sbt_track_states *out, void *stream);
 
 /* ---- serving ---------------------------------------------------------------------
  * Continuous batching of single events that arrive over time.  The server

@@ -1,8 +1,10 @@
 """Search by triplet CPU oracle (test infrastructure only).
 
-Plain single-threaded C (``sbt_oracle.c``) behind ctypes.  Only the test
-suite, the smoke check and the benchmark's CPU-baseline leg may import this
-package; the HIP library never does.
+Plain single-threaded C (``sbt_oracle.c``) behind ctypes; the steps around
+the method in the paper's sequence (global event cut, consolidation) are plain
+float64 numpy in ``sequence.py``.  Only the test suite, the smoke check and the
+benchmark's CPU-baseline leg may import this package; the HIP library never
+does.
 
 ``build()`` compiles ``liboracle.so`` with gcc at -O2, -ffp-contract=off and
 no fast-math, so binary32 arithmetic is evaluated exactly as written.
@@ -31,6 +33,7 @@ DEFAULTS = dict(
     max_scatter_forwarding=0.04,
     max_tracklet_chi2=0.002,
     max_consecutive_misses=1,
+    max_event_hits=0,
 )
 
 
@@ -69,7 +72,7 @@ def lib():
         L.sbt_oracle_reconstruct.restype = ctypes.c_int
         L.sbt_oracle_reconstruct.argtypes = (
             [ctypes.c_int32, f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-             ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+             ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
              ctypes.c_int32, i32p, i32p, f32p, f32p, f32p, i32p, i32p, i32p])
         _lib = L
     return _lib
@@ -139,7 +142,7 @@ def reconstruct(batch, **overrides):
         M, _p(mz, ctypes.c_float), int(p["reverse"]), int(p["max_doublet_candidates"]),
         int(p["phi_window_seeding"]), int(p["phi_window_forwarding"]),
         float(p["max_scatter_seeding"]), float(p["max_scatter_forwarding"]),
-        float(p["max_tracklet_chi2"]), int(p["max_consecutive_misses"]),
+        float(p["max_tracklet_chi2"]), int(p["max_consecutive_misses"]), int(p["max_event_hits"]),
         E, _p(eo, ctypes.c_int32), _p(mo, ctypes.c_int32),
         _p(x, ctypes.c_float), _p(y, ctypes.c_float), _p(z, ctypes.c_float),
         _p(eto, ctypes.c_int32), _p(tho, ctypes.c_int32), _p(th, ctypes.c_int32))

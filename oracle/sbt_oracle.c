@@ -484,6 +484,8 @@ static int32_t orc_event_run(const orc_params *p, int N, const int32_t *mo,
 
 /* Full batch reconstruction.
  *   module_z[M], event_offsets[E+1], module_offsets[E*M+1] (absolute), x/y/z[H]
+ *   max_event_hits > 0: the global event cut of the paper's sequence
+ *   (Section 4): an event with more hits is not reconstructed (no tracks).
  *   outputs: event_track_offsets[E+1], track_hit_offsets[floor(H/3)+1],
  *            track_hits[H] (event-local ids, traversal order).
  * Returns 0 or a negative error. */
@@ -492,6 +494,7 @@ int sbt_oracle_reconstruct(int32_t n_modules, const float *module_z, int32_t rev
                            int32_t phi_window_seeding, int32_t phi_window_forwarding,
                            float max_scatter_seeding, float max_scatter_forwarding,
                            float max_tracklet_chi2, int32_t max_consecutive_misses,
+                           int32_t max_event_hits,
                            int32_t n_events, const int32_t *event_offsets,
                            const int32_t *module_offsets,
                            const float *x, const float *y, const float *z,
@@ -499,7 +502,7 @@ int sbt_oracle_reconstruct(int32_t n_modules, const float *module_z, int32_t rev
                            int32_t *track_hits)
 {
     if (n_modules < 3 || n_modules > ORC_MAX_MODULES || !module_z || n_events < 0) return ORC_ERR_INVALID_ARG;
-    if (max_doublet_candidates < 1 || max_consecutive_misses < 0) return ORC_ERR_INVALID_ARG;
+    if (max_doublet_candidates < 1 || max_consecutive_misses < 0 || max_event_hits < 0) return ORC_ERR_INVALID_ARG;
     if (phi_window_seeding < 0 || phi_window_seeding > 32767) return ORC_ERR_INVALID_ARG;
     if (phi_window_forwarding < 0 || phi_window_forwarding > 32767) return ORC_ERR_INVALID_ARG;
     orc_params p;
@@ -515,6 +518,10 @@ int sbt_oracle_reconstruct(int32_t n_modules, const float *module_z, int32_t rev
     for (int32_t e = 0; e < n_events; ++e) {
         int32_t base = event_offsets[e];
         int32_t N = event_offsets[e + 1] - base;
+        if (max_event_hits > 0 && N > max_event_hits) {
+            event_track_offsets[e + 1] = n_tracks;
+            continue;
+        }
         for (int k = 0; k <= n_modules; ++k) mo[k] = module_offsets[(int64_t)e * n_modules + k] - base;
         int32_t nh = 0;
         int32_t nt = orc_event_run(&p, N, mo, x + base, y + base, z + base,

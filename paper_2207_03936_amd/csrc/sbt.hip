@@ -13,6 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
+#include <functional>
 #include <vector>
 
 #include "sbt.h"
@@ -173,6 +175,125 @@ __global__ __launch_bounds__(kWriteThreads) void k_write_events(HitsArgs H, Work
         int32_t *tho = O.tho + I.out_t + e;
         for (int i = threadIdx.x; i <= I.nt; i += kWriteThreads) tho[i] = i < I.nt ? ws_toff(W)[hb + i] : I.nh;
         for (int j = threadIdx.x; j < I.nh; j += kWriteThreads) O.th[I.out_h + j] = ws_sthits(W)[hb + j];
+    }
+}
+
+// Consolidation: one workgroup per event, one lane per track.  The lane
+// copies the coordinates of its track's hits in track order, then fits
+// x(z) and y(z) by unweighted least squares: means, sums centred on the
+// means, residuals, each accumulated over the hits in track order (binary32,
+// no contraction, correctly rounded division).  A track of up to
+// kConsRegHits hits is loaded into registers at once (every load in flight
+// together); a longer one is read again from the inputs for each pass.
+constexpr int kConsThreads = 256;
+constexpr int kConsRegHits = 32;
+
+__device__ __forceinline__ void write_state(float *__restrict__ state, int t, float xm, float ym, float zm, float tx,
+                                            float ty, float c2, int n)
+{
+    float *st = state + 6 * (size_t)t;
+    st[0] = xm;
+    st[1] = ym;
+    st[2] = zm;
+    st[3] = tx;
+    st[4] = ty;
+    st[5] = c2 / (float)(2 * n - 4);
+}
+
+__global__ __launch_bounds__(kConsThreads) void k_consolidate(HitsArgs H, const int32_t *__restrict__ eto,
+                                                              const int32_t *__restrict__ tho,
+                                                              const int32_t *__restrict__ th,
+                                                              float *__restrict__ px, float *__restrict__ py,
+                                                              float *__restrict__ pz, float *__restrict__ state)
+{
+    const float *__restrict__ X = H.x;
+    const float *__restrict__ Y = H.y;
+    const float *__restrict__ Z = H.z;
+    for (int e = blockIdx.x; e < H.n_events; e += gridDim.x) {
+        const int hb = H.eo[e];
+        const int t1 = eto[e + 1];
+        for (int t = eto[e] + (int)threadIdx.x; t < t1; t += kConsThreads) {
+            const int lo = tho[t], hi = tho[t + 1];
+            const int n = hi - lo;
+            const float fn = (float)n;
+            if (n <= kConsRegHits) {
+                int id[kConsRegHits];
+                float xs[kConsRegHits], ys[kConsRegHits], zs[kConsRegHits];
+#pragma unroll
+                for (int j = 0; j < kConsRegHits; ++j)
+                    if (j < n) id[j] = hb + th[lo + j];
+#pragma unroll
+                for (int j = 0; j < kConsRegHits; ++j)
+                    if (j < n) {
+                        xs[j] = X[id[j]];
+                        ys[j] = Y[id[j]];
+                        zs[j] = Z[id[j]];
+                    }
+                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+                for (int j = 0; j < kConsRegHits; ++j)
+                    if (j < n) {
+                        px[lo + j] = xs[j];
+                        py[lo + j] = ys[j];
+                        pz[lo + j] = zs[j];
+                        sx = sx + xs[j];
+                        sy = sy + ys[j];
+                        sz = sz + zs[j];
+                    }
+                const float xm = sx / fn, ym = sy / fn, zm = sz / fn;
+                float szz = 0.0f, sxz = 0.0f, syz = 0.0f;
+#pragma unroll
+                for (int j = 0; j < kConsRegHits; ++j)
+                    if (j < n) {
+                        const float dz = zs[j] - zm;
+                        szz = szz + dz * dz;
+                        sxz = sxz + dz * (xs[j] - xm);
+                        syz = syz + dz * (ys[j] - ym);
+                    }
+                const float tx = sxz / szz, ty = syz / szz;
+                float c2 = 0.0f;
+#pragma unroll
+                for (int j = 0; j < kConsRegHits; ++j)
+                    if (j < n) {
+                        const float dz = zs[j] - zm;
+                        const float rx = xs[j] - (xm + tx * dz);
+                        const float ry = ys[j] - (ym + ty * dz);
+                        c2 = c2 + ((rx * rx) + (ry * ry));
+                    }
+                write_state(state, t, xm, ym, zm, tx, ty, c2, n);
+                continue;
+            }
+            float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+            for (int k = lo; k < hi; ++k) {
+                const int i = hb + th[k];
+                const float x = X[i], y = Y[i], z = Z[i];
+                px[k] = x;
+                py[k] = y;
+                pz[k] = z;
+                sx = sx + x;
+                sy = sy + y;
+                sz = sz + z;
+            }
+            const float xm = sx / fn, ym = sy / fn, zm = sz / fn;
+            float szz = 0.0f, sxz = 0.0f, syz = 0.0f;
+            for (int k = lo; k < hi; ++k) {
+                const int i = hb + th[k];
+                const float dz = Z[i] - zm;
+                szz = szz + dz * dz;
+                sxz = sxz + dz * (X[i] - xm);
+                syz = syz + dz * (Y[i] - ym);
+            }
+            const float tx = sxz / szz, ty = syz / szz;
+            float c2 = 0.0f;
+            for (int k = lo; k < hi; ++k) {
+                const int i = hb + th[k];
+                const float dz = Z[i] - zm;
+                const float rx = X[i] - (xm + tx * dz);
+                const float ry = Y[i] - (ym + ty * dz);
+                c2 = c2 + ((rx * rx) + (ry * ry));
+            }
+            write_state(state, t, xm, ym, zm, tx, ty, c2, n);
+        }
     }
 }
 
@@ -427,6 +548,7 @@ int sbt_params_validate(const sbt_params *p)
     if (p->phi_window_forwarding < 0 || p->phi_window_forwarding > 32767) return SBT_ERR_INVALID_ARG;
     if (p->max_consecutive_misses < 0) return SBT_ERR_INVALID_ARG;
     if (p->reverse != 0 && p->reverse != 1) return SBT_ERR_INVALID_ARG;
+    if (p->max_event_hits < 0) return SBT_ERR_INVALID_ARG;
     // nominal z strictly monotone in the module index
     bool inc = true, dec = true;
     for (int k = 1; k < p->n_modules; ++k) {
@@ -501,6 +623,39 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
                        lds_bytes(kPlainCap, kPlainOwnCap), s, *params, H, W, lds_sortcap(kPlainCap, kPlainOwnCap));
     hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
                        phi_sorted, ids_sorted);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+int sbt_gec_threshold(int32_t n_events, const int32_t *event_offsets, double fraction, int32_t *max_hits)
+{
+    if (n_events < 0 || !max_hits || !(fraction >= 0.0 && fraction <= 1.0)) return SBT_ERR_INVALID_ARG;
+    if (n_events > 0 && !event_offsets) return SBT_ERR_INVALID_ARG;
+    const int64_t k = (int64_t)std::floor(fraction * (double)n_events);
+    std::vector<int32_t> sizes((size_t)n_events);
+    for (int32_t e = 0; e < n_events; ++e) {
+        sizes[(size_t)e] = event_offsets[e + 1] - event_offsets[e];
+        if (sizes[(size_t)e] < 0) return SBT_ERR_INVALID_ARG;
+    }
+    if (k >= n_events) {
+        *max_hits = 1;
+        return SBT_OK;
+    }
+    // the (k+1)-th largest size: at most k sizes exceed it, k+1 exceed anything smaller
+    std::nth_element(sizes.begin(), sizes.begin() + k, sizes.end(), std::greater<int32_t>());
+    *max_hits = std::max(1, sizes[(size_t)k]);
+    return SBT_OK;
+}
+
+int sbt_consolidate(const sbt_hits *hits, const sbt_tracks *tracks, sbt_track_states *out, void *stream)
+{
+    int rc;
+    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
+    if (!out || !out->hit_x || !out->hit_y || !out->hit_z || !out->state) return SBT_ERR_INVALID_ARG;
+    if (hits->n_events == 0) return SBT_OK;
+    const HitsArgs H = hits_args(hits);
+    hipLaunchKernelGGL(k_consolidate, dim3(std::min(H.n_events, 8192)), dim3(kConsThreads), 0, (hipStream_t)stream,
+                       H, tracks->event_track_offsets, tracks->track_hit_offsets, tracks->track_hits, out->hit_x,
+                       out->hit_y, out->hit_z, out->state);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
 }
 

@@ -552,6 +552,7 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
     unsigned st = 0;
     if (lo < 0 || hi > H.n_hits || hi < lo) st = SBT_EV_BAD_OFFSETS;
     else if (hi - lo > SBT_MAX_EVENT_HITS) st = SBT_EV_TOO_LARGE;
+    else if (P.max_event_hits > 0 && hi - lo > P.max_event_hits) st = SBT_EV_CUT;
     if (st == 0) {
         const long long base = (long long)e * M;
         for (int k = threadIdx.x; k <= M; k += B) {

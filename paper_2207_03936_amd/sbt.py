@@ -31,6 +31,8 @@ SBT_ERR_NOMEM = -5
 SBT_ERR_NOT_READY = -6
 SBT_EV_TOO_LARGE = 1
 SBT_EV_BAD_OFFSETS = 2
+SBT_EV_INTERNAL = 4
+SBT_EV_CUT = 8
 
 DEFAULT_PARAMS = dict(
     reverse=1,
@@ -41,6 +43,7 @@ DEFAULT_PARAMS = dict(
     max_scatter_forwarding=0.04,
     max_tracklet_chi2=0.002,
     max_consecutive_misses=1,
+    max_event_hits=0,
 )
 
 
@@ -54,7 +57,8 @@ class SbtParams(ctypes.Structure):
                 ("max_scatter_seeding", ctypes.c_float),
                 ("max_scatter_forwarding", ctypes.c_float),
                 ("max_tracklet_chi2", ctypes.c_float),
-                ("max_consecutive_misses", ctypes.c_int32)]
+                ("max_consecutive_misses", ctypes.c_int32),
+                ("max_event_hits", ctypes.c_int32)]
 
 
 class SbtHits(ctypes.Structure):
@@ -72,6 +76,11 @@ class SbtHitsF16(ctypes.Structure):
 class SbtTracks(ctypes.Structure):
     _fields_ = [("event_track_offsets", ctypes.c_void_p), ("track_hit_offsets", ctypes.c_void_p),
                 ("track_hits", ctypes.c_void_p), ("event_status", ctypes.c_void_p)]
+
+
+class SbtTrackStates(ctypes.Structure):
+    _fields_ = [("hit_x", ctypes.c_void_p), ("hit_y", ctypes.c_void_p), ("hit_z", ctypes.c_void_p),
+                ("state", ctypes.c_void_p)]
 
 
 class SbtTuning(ctypes.Structure):
@@ -128,6 +137,8 @@ PROTOTYPES = {
                                          _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float),
                                          _P(ctypes.c_double), _P(ctypes.c_int32), _P(ctypes.c_double)]),
     "sbt_now_us": (ctypes.c_double, []),
+    "sbt_gec_threshold": (ctypes.c_int, [ctypes.c_int32, _P(ctypes.c_int32), ctypes.c_double, _P(ctypes.c_int32)]),
+    "sbt_consolidate": (ctypes.c_int, [_P(SbtHits), _P(SbtTracks), _P(SbtTrackStates), _VP]),
 }
 
 _lib = None
@@ -330,6 +341,47 @@ def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None):
                                     ctypes.c_void_p(ws.ptr), ws.bytes, _stream_handle(stream)), "sbt_debug_phi_sort")
     n = batch.n_hits
     return (phi[:n].cpu().numpy().view(np.uint16), ids[:n].cpu().numpy().view(np.uint16))
+
+
+# ------------------------------------------------------------------ sequence steps
+
+def sbt_gec_threshold(event_offsets, fraction: float) -> int:
+    """Hit-count threshold of the global event cut (host computation)."""
+    eo = np.ascontiguousarray(event_offsets, dtype=np.int32)
+    out = ctypes.c_int32(0)
+    _check(lib().sbt_gec_threshold(int(eo.size - 1), eo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   float(fraction), ctypes.byref(out)), "sbt_gec_threshold")
+    return int(out.value)
+
+
+class TrackStates:
+    """Output buffers of sbt_consolidate sized for a batch of n_hits hits."""
+
+    def __init__(self, n_hits, device="cuda", pinned=False):
+        torch = _torch()
+        kw = dict(dtype=torch.float32, pin_memory=True) if pinned else dict(dtype=torch.float32, device=device)
+        n = max(int(n_hits), 1)
+        self.hit_x = torch.zeros(n, **kw)
+        self.hit_y = torch.zeros(n, **kw)
+        self.hit_z = torch.zeros(n, **kw)
+        self.state = torch.zeros(6 * max(int(n_hits) // 3, 1), **kw)
+        self.states = SbtTrackStates(self.hit_x.data_ptr(), self.hit_y.data_ptr(), self.hit_z.data_ptr(),
+                                     self.state.data_ptr())
+
+    def to_host(self, n_tracks, n_track_hits):
+        """(hit_x, hit_y, hit_z, state[n_tracks, 6]) trimmed, as numpy (synchronises)."""
+        a = int(n_track_hits)
+        return (self.hit_x[:a].cpu().numpy(), self.hit_y[:a].cpu().numpy(), self.hit_z[:a].cpu().numpy(),
+                self.state[:6 * int(n_tracks)].cpu().numpy().reshape(-1, 6))
+
+
+def sbt_consolidate(batch: DeviceBatch, tracks: DeviceTracks, out: Optional[TrackStates] = None,
+                    stream=None) -> TrackStates:
+    """Packed track coordinates and straight-line states (asynchronous)."""
+    out = out or TrackStates(batch.n_hits)
+    _check(lib().sbt_consolidate(ctypes.byref(batch.hits), ctypes.byref(tracks.tracks), ctypes.byref(out.states),
+                                 _stream_handle(stream)), "sbt_consolidate")
+    return out
 
 
 # ------------------------------------------------------------------ batched form

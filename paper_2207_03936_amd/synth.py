@@ -25,6 +25,10 @@ Event recipes (``CONFIGS``):
 * ``mu30``   - Poisson(30) vertices, 97 % hit efficiency, 5 % noise, 20 % of
   tracks get a N(0, 2 mrad) kink in both slopes at one crossed plane
   (about 12,000 hits per event).
+* ``pairs7.6`` - the ``mu7.6`` mixture on module pairs: each traversal plane is
+  two half-planes, x < 0 at z - 6 mm and x >= 0 at z + 6 mm, so the hits of
+  one module carry two z values, neither equal to the module's nominal z (the
+  method treats a pair as one module, Section 3).
 
 Hits of an event are grouped by plane index ascending and shuffled within a
 plane; a hit's event-local ID is its position in the event.  The random stream
@@ -61,6 +65,7 @@ class Recipe:
     noise_fraction: float = 0.01
     kink_fraction: float = 0.0
     kink_sigma: float = 0.002
+    half_dz: float = 0.0    # > 0: module pairs, half-planes at z -/+ half_dz by the sign of x
 
 
 CONFIGS = {
@@ -70,6 +75,7 @@ CONFIGS = {
     "mu30": Recipe("mu30", 4, 2000, "poisson", pv_mean=30.0,
                    efficiency=0.97, noise_fraction=0.05, kink_fraction=0.2),
     "serve": Recipe("serve", 5, 0, "uniform", pv_max=25),
+    "pairs7.6": Recipe("pairs7.6", 6, 1000, "poisson", pv_mean=7.6, half_dz=6.0),
 }
 
 
@@ -173,6 +179,10 @@ def make_event(recipe: Recipe, index: int) -> dict:
     ty = np.tan(theta) * np.sin(phi)
 
     zp = PLANE_Z[None, :]
+    if recipe.half_dz > 0.0:
+        # the half-plane a track crosses follows the sign of x at the nominal plane
+        xn = xv[:, None] + tx[:, None] * (zp - zv[:, None])
+        zp = zp + np.where(xn >= 0.0, recipe.half_dz, -recipe.half_dz)
     crossed = zp > zv[:, None]                               # [T, P]
     px = xv[:, None] + tx[:, None] * (zp - zv[:, None])
     py = yv[:, None] + ty[:, None] * (zp - zv[:, None])
@@ -187,7 +197,8 @@ def make_event(recipe: Recipe, index: int) -> dict:
             planes = np.nonzero(crossed[t])[0]
             kp = planes[min(int(pick[t] * planes.size), planes.size - 1)]
             after = np.arange(N_PLANES) > kp
-            dz = PLANE_Z[after] - PLANE_Z[kp]
+            zt = np.broadcast_to(zp, (T, N_PLANES))[t]
+            dz = zt[after] - zt[kp]
             px[t, after] = px[t, kp] + (tx[t] + dtx[t]) * dz
             py[t, after] = py[t, kp] + (ty[t] + dty[t]) * dz
 
@@ -200,13 +211,19 @@ def make_event(recipe: Recipe, index: int) -> dict:
 
     tid, plane = np.nonzero(keep)
     hx, hy = sx[tid, plane], sy[tid, plane]
+    hz = np.broadcast_to(zp, (T, N_PLANES))[tid, plane]
     n_noise = int(round(recipe.noise_fraction * tid.size))
     nplane = rng.integers(0, N_PLANES, n_noise)
     nr = np.sqrt(rng.uniform(R_MIN * R_MIN, R_MAX * R_MAX, n_noise))
     nphi = rng.uniform(0.0, 2.0 * np.pi, n_noise)
+    nx = nr * np.cos(nphi)
+    nz = PLANE_Z[nplane]
+    if recipe.half_dz > 0.0:
+        nz = nz + np.where(nx >= 0.0, recipe.half_dz, -recipe.half_dz)
     all_plane = np.concatenate([plane, nplane])
-    all_x = np.concatenate([hx, nr * np.cos(nphi)])
+    all_x = np.concatenate([hx, nx])
     all_y = np.concatenate([hy, nr * np.sin(nphi)])
+    all_z = np.concatenate([hz, nz])
     all_truth = np.concatenate([tid, np.full(n_noise, -1)])
     # group by plane ascending, random order within a plane
     order = np.lexsort((rng.random(all_plane.size), all_plane))
@@ -214,7 +231,7 @@ def make_event(recipe: Recipe, index: int) -> dict:
     counts = np.bincount(all_plane, minlength=N_PLANES).astype(np.int64)
     return dict(x=all_x[order].astype(np.float32),
                 y=all_y[order].astype(np.float32),
-                z=PLANE_Z[all_plane].astype(np.float32),
+                z=all_z[order].astype(np.float32),
                 module_counts=counts,
                 truth=all_truth[order].astype(np.int32))
 

@@ -362,6 +362,20 @@ def test_repeat_runs_identical():
 
 
 @pytest.mark.parametrize("form", ["plain", "batched", "f16"])
+def test_module_pairs_match_oracle(form):
+    """Module pairs: hits of a module at two z values, neither the nominal one."""
+    import torch
+    say(f"module pairs, {form}")
+    b = synth.make_batch("pairs7.6", 40)
+    if form == "plain":
+        _same(run_plain(b), oracle.reconstruct(b), "pairs plain")
+    elif form == "batched":
+        _same(run_batched(b), oracle.reconstruct(b), "pairs batched")
+    else:
+        _same(run_batched_f16(b), oracle.reconstruct(rounded_to_f16(b)), "pairs f16")
+
+
+@pytest.mark.parametrize("form", ["plain", "batched", "f16"])
 def test_outputs_in_pinned_host_memory(form):
     """Tracks written by the kernels straight into pinned host buffers equal
     the oracle's (the kernels only write the outputs, never read them)."""
