@@ -173,6 +173,35 @@ def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False, s
                      "; hits in pinned host memory before, tracks written by the kernels into pinned host memory")
 
 
+def plain_streams_leg(torch, sbt, params, batch, steps, warmup, streams):
+    """The paper's way to fill the device with the plain per-event kernels
+    (Section 4: t streams, each running the sequence over its own n events):
+    the batch split into n_streams contiguous slices, each reconstructed by
+    the plain form on a stream of its own, all in flight together."""
+    n_streams = len(streams)
+    E = batch.n_events
+    cuts = np.linspace(0, E, n_streams + 1).astype(int)
+    parts = [batch.select(range(cuts[i], cuts[i + 1])) for i in range(n_streams)]
+    devs = [sbt.DeviceBatch(b) for b in parts]
+    outs = [sbt.DeviceTracks(b.n_events, b.n_hits) for b in parts]
+    wss = [sbt.Workspace(b.n_events, b.n_hits) for b in parts]
+
+    def step():
+        for i in range(n_streams):
+            with torch.cuda.stream(streams[i]):
+                sbt.sbt_reconstruct(params, devs[i], outs[i], wss[i], streams[i])
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    return dict(streams=n_streams, events_per_stream=int(cuts[1] - cuts[0]), events_per_s=round(E / sec, 1),
+                ms_per_step=round(sec * 1e3, 4))
+
+
 def sequence_leg(torch, sbt, params, tuning, batch, steps, streams, fraction=0.1):
     """The paper's sequence around the method (Section 4), decoding aside:
     global event cut, H2D copy of the hits from pinned host memory,
@@ -390,6 +419,11 @@ def main():
     sec_plain = timed(lambda: sbt.sbt_reconstruct(params, dev, out, ws), args.steps, args.warmup)
     got_plain = out.to_host()
     same_paths = all(np.array_equal(a, b) for a, b in zip(got[:3], got_plain[:3]))
+    # three streams for every multi-stream leg: with the null stream they take the four hardware
+    # queues HIP opens by default, so no two busy streams share a queue
+    extra_streams = [torch.cuda.Stream() for _ in range(3)]
+    plain_multi = [plain_streams_leg(torch, sbt, params, batch, args.steps, args.warmup, extra_streams[:t])
+                   for t in (2, 3)]
 
     # dominant kernel duration: HIP events around the persistent kernel on the
     # stream it is launched on (profiling mode launches without the graph)
@@ -409,7 +443,7 @@ def main():
     sq = measured_sq(H)
     if not args.no_e2e:
         e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
-        pipe_streams = [torch.cuda.Stream() for _ in range(2)]
+        pipe_streams = extra_streams[:2]
         e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
                            streams=pipe_streams)
     # half-precision array-of-structures input (the paper's hit-storage optimisation)
@@ -442,6 +476,7 @@ def main():
         "hits_per_s": round(H / sec_batched, 1),
         "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
                   "hits_per_s": round(H / sec_plain, 1)},
+        "plain_streams": plain_multi,
         "batched_over_plain": round(sec_plain / sec_batched, 3),
         "plain_equals_batched": bool(same_paths),
         "stage_ms": {"k_persistent": round(k_ms, 4), "k_scan": round(float(stage[1]), 4),
