@@ -25,6 +25,8 @@ Event recipes (``CONFIGS``):
 * ``mu30``   - Poisson(30) vertices, 97 % hit efficiency, 5 % noise, 20 % of
   tracks get a N(0, 2 mrad) kink in both slopes at one crossed plane
   (about 12,000 hits per event).
+* ``bw7.6``  - the ``mu7.6`` mixture with a quarter of the tracks flying
+  backwards (towards -z, through the planes upstream of their vertex).
 * ``pairs7.6`` - the ``mu7.6`` mixture on module pairs: each traversal plane is
   two half-planes, x < 0 at z - 6 mm and x >= 0 at z + 6 mm, so the hits of
   one module carry two z values, neither equal to the module's nominal z (the
@@ -66,6 +68,7 @@ class Recipe:
     kink_fraction: float = 0.0
     kink_sigma: float = 0.002
     half_dz: float = 0.0    # > 0: module pairs, half-planes at z -/+ half_dz by the sign of x
+    backward_fraction: float = 0.0   # tracks flying towards -z
 
 
 CONFIGS = {
@@ -76,6 +79,7 @@ CONFIGS = {
                    efficiency=0.97, noise_fraction=0.05, kink_fraction=0.2),
     "serve": Recipe("serve", 5, 0, "uniform", pv_max=25),
     "pairs7.6": Recipe("pairs7.6", 6, 1000, "poisson", pv_mean=7.6, half_dz=6.0),
+    "bw7.6": Recipe("bw7.6", 7, 1000, "poisson", pv_mean=7.6, backward_fraction=0.25),
 }
 
 
@@ -183,9 +187,19 @@ def make_event(recipe: Recipe, index: int) -> dict:
         # the half-plane a track crosses follows the sign of x at the nominal plane
         xn = xv[:, None] + tx[:, None] * (zp - zv[:, None])
         zp = zp + np.where(xn >= 0.0, recipe.half_dz, -recipe.half_dz)
-    crossed = zp > zv[:, None]                               # [T, P]
-    px = xv[:, None] + tx[:, None] * (zp - zv[:, None])
-    py = yv[:, None] + ty[:, None] * (zp - zv[:, None])
+    if recipe.backward_fraction > 0.0:
+        # a backward track crosses the planes below its vertex; its transverse
+        # offset grows with the distance flown
+        assert recipe.kink_fraction == 0.0 and recipe.half_dz == 0.0
+        back = rng.random(T) < recipe.backward_fraction
+        flown = np.where(back[:, None], zv[:, None] - zp, zp - zv[:, None])
+        crossed = flown > 0.0
+        px = xv[:, None] + tx[:, None] * flown
+        py = yv[:, None] + ty[:, None] * flown
+    else:
+        crossed = zp > zv[:, None]                           # [T, P]
+        px = xv[:, None] + tx[:, None] * (zp - zv[:, None])
+        py = yv[:, None] + ty[:, None] * (zp - zv[:, None])
 
     if recipe.kink_fraction > 0.0 and T > 0:
         kinked = rng.random(T) < recipe.kink_fraction

@@ -361,6 +361,14 @@ def test_repeat_runs_identical():
     ctx.close()
 
 
+@pytest.mark.parametrize("form", ["plain", "batched"])
+def test_backward_tracks_match_oracle(form):
+    say(f"backward tracks, {form}")
+    b = synth.make_batch("bw7.6", 40)
+    got = run_plain(b) if form == "plain" else run_batched(b)
+    _same(got, oracle.reconstruct(b), f"backward {form}")
+
+
 @pytest.mark.parametrize("form", ["plain", "batched", "f16"])
 def test_module_pairs_match_oracle(form):
     """Module pairs: hits of a module at two z values, neither the nominal one."""

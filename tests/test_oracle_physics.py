@@ -148,6 +148,30 @@ def test_indicators_module_pairs():
     assert r["hit_efficiency"] >= 0.98
 
 
+def test_backward_tracks_are_found():
+    """A quarter of the tracks fly towards -z, through the planes upstream of
+    their vertex, the other way through the traversal: straight lines all the
+    same.  Particles confined to the upstream planes (z <= -35 mm) are the
+    backward ones; at least 99 % of those with three consecutive hits are
+    found."""
+    b = synth.make_batch("bw7.6", 20)
+    M = b.n_modules
+    tracks = tracks_per_event(*oracle.reconstruct(b))
+    n_back = n_found = 0
+    for e in range(b.n_events):
+        lo, hi = int(b.event_offsets[e]), int(b.event_offsets[e + 1])
+        truth = b.truth[lo:hi]
+        mod = np.repeat(np.arange(M), np.diff(b.module_offsets[e * M:(e + 1) * M + 1]))
+        for p in np.unique(truth[truth >= 0]):
+            m = np.unique(mod[truth == p])
+            if m.max() <= 6 and m.size >= 3 and np.all(np.diff(m) == 1):
+                n_back += 1
+                ids = set(np.nonzero(truth == p)[0].tolist())
+                n_found += any(len(ids & set(t)) >= 0.7 * len(t) for t in tracks[e])
+    assert n_back > 500 and n_found >= 0.99 * n_back
+    check_invariants(b, oracle.reconstruct(b))
+
+
 def test_golden_tracks_unchanged():
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "tiny_event0_tracks.txt")
