@@ -335,11 +335,14 @@ def test_f16_rejects_misaligned_coordinates():
     ctx.close()
 
 
-@pytest.mark.parametrize("config,n,sample", [("mu1-25", 10000, 120), ("mu30", 2000, 30)])
-def test_full_size_sampled(config, n, sample):
-    say(f"full {config} x{n}, {sample} sampled events")
+# full batches in the launch configurations the autotuner picks for them
+@pytest.mark.parametrize("config,n,sample,tuning", [("mu1-25", 10000, 120, (512, 2, 672)),
+                                                   ("mu30", 2000, 30, (1024, 1, 1536)),
+                                                   ("mu30", 2000, 30, (512, 2, 672))])
+def test_full_size_sampled(config, n, sample, tuning):
+    say(f"full {config} x{n}, {sample} sampled events, tuning {tuning}")
     b = synth.make_batch(config, n)
-    got = run_batched(b)
+    got = run_batched(b, sbt.make_tuning(*tuning))
     assert not got[3].any()
     rng = np.random.default_rng(5)
     events = np.sort(rng.choice(b.n_events, sample, replace=False))
