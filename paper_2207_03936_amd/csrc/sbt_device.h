@@ -922,10 +922,13 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
     const uint16_t lo = (uint16_t)(qe - Ws);
     int pc = win_lower_bound<kLds>(wc, lo);
     if (pc == nc) pc = 0;
+    Hit16 h2n = at(wc.h, pc);
     for (int jj = 0; jj < nc; ++jj) {
         // LDS: the flag bit is addressed by position, so it loads alongside the hit
         const bool fpos = kLds ? ((at(cfree, (uint32_t)pc >> 6) >> (pc & 63)) & 1ull) != 0ull : true;
-        const Hit16 h2 = at(wc.h, pc);
+        const Hit16 h2 = h2n;
+        const int pn = pc + 1 == nc ? 0 : pc + 1;
+        h2n = at(wc.h, pn);   // the next position, loaded while this one is scored
         if ((uint16_t)(q_of(h2) - lo) > span) break;
         const uint32_t id2 = id_of(h2);
         const bool fr = kLds ? fpos : is_free(own, id2);
@@ -937,7 +940,7 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
         const bool better = fr && (sc < Ss) && (k < bkey);
         bkey = better ? k : bkey;
         bpos = better ? ((uint32_t)pos0 | ((uint32_t)pc << 16)) : bpos;
-        pc = pc + 1 == nc ? 0 : pc + 1;
+        pc = pn;
     }
 }
 
@@ -972,8 +975,11 @@ __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, flo
         // flag test of the method is therefore always passed here.
         // (scatter, id) packed so that one comparison orders both
         unsigned long long bk = ~0ull;
+        Hit16 hn = at(wc.h, pc);
         for (int j = 0; j < nc; ++j) {
-            const Hit16 h = at(wc.h, pc);
+            const Hit16 h = hn;
+            const int pn = pc + 1 == nc ? 0 : pc + 1;
+            hn = at(wc.h, pn);   // the next position, loaded while this one is scored
             if ((uint16_t)(q_of(h) - lo) > span) break;
             const float dz = h.z - R.zb;
             const float dx = (R.xb + R.tx * dz) - h.x;
@@ -983,7 +989,7 @@ __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, flo
             const bool better = (sc < Sf) && (k < bk);
             bk = better ? k : bk;
             bpos = better ? pc : bpos;
-            pc = pc + 1 == nc ? 0 : pc + 1;
+            pc = pn;
         }
         if (bk != ~0ull) {
             best = (uint16_t)(bk & 0xFFFFu);
