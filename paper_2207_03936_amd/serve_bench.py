@@ -59,8 +59,9 @@ def main(argv=None):
     ap.add_argument("--budget-gib", type=float, default=8.0)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--slot-events", type=int, default=512)
-    ap.add_argument("--slot-hits", type=int, default=1 << 21)
+    ap.add_argument("--slot-hits", type=int, default=3 << 20)
     ap.add_argument("--max-wait-us", type=int, default=300)
+    ap.add_argument("--max-events", type=int, default=40_000_000, help="cap on arrivals per rate")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "serving needs a GPU"
@@ -74,7 +75,7 @@ def main(argv=None):
     for r in args.rates.split(","):
         r = float(r)
         rate = r * cap if r <= 1.0 else r
-        res = run_rate(srv, pool, rate, args.seconds)
+        res = run_rate(srv, pool, rate, args.seconds, max_events=args.max_events)
         print(json.dumps(dict(kind="poisson", fraction_of_saturation=round(rate / cap, 4), **res)), flush=True)
     srv.close()
 
