@@ -634,6 +634,8 @@ __device__ __forceinline__ int sort_bin(const int *mo, const uint8_t *mtab, int 
     return m * bpm + (q >> shift);
 }
 
+constexpr int kSortChunk = 8;
+
 template <int B>
 __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0, Shared<B> &S, int sortcap)
 {
@@ -653,15 +655,23 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     const HitSrc src = hit_src(H, v.hb);
     // memory form: bins in the claim words (not yet in use)
     uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
-    for (int i = threadIdx.x; i < N; i += B) {
-        float px, py;
-        src.xy(i, px, py);
-        const uint16_t qi = phi16(px, py);
-        const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
-        const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
-        if (form == 0) lkeys[N + i] = tb;
-        else if (form == 2) at(bins_m, i) = tb;
-        atomicAdd(&hist[bin], 1);
+    // the coordinates of a lane's next kSortChunk hits are loaded together
+    for (int i0 = threadIdx.x; i0 < N; i0 += kSortChunk * B) {
+        float px[kSortChunk], py[kSortChunk];
+#pragma unroll
+        for (int j = 0; j < kSortChunk; ++j)
+            if (i0 + j * B < N) src.xy(i0 + j * B, px[j], py[j]);
+#pragma unroll
+        for (int j = 0; j < kSortChunk; ++j) {
+            const int i = i0 + j * B;
+            if (i >= N) break;
+            const uint16_t qi = phi16(px[j], py[j]);
+            const int bin = sort_bin(S.mo, S.mtab, i, qi, bpm, shift);
+            const uint32_t tb = (uint32_t)qi | ((uint32_t)bin << 16);
+            if (form == 0) lkeys[N + i] = tb;
+            else if (form == 2) at(bins_m, i) = tb;
+            atomicAdd(&hist[bin], 1);
+        }
     }
     __syncthreads();
     block_scan_inplace<B>(hist, nb + 1, S.scan);
