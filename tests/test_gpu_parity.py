@@ -412,3 +412,45 @@ def test_outputs_in_pinned_host_memory(form):
     got = out.to_host()
     _same(got, want, f"pinned {form}")
     assert not got[3].any()
+
+
+def _line_events(rng, M, n_events, n_tracks, noise, pitch=20.0):
+    """Straight tracks from near the axis over M planes plus uniform noise."""
+    mz = (-300.0 + pitch * np.arange(M)).astype(np.float32)
+    events = []
+    for _ in range(n_events):
+        per = [[] for _ in range(M)]
+        for _ in range(n_tracks):
+            phi = rng.uniform(-np.pi, np.pi)
+            slope = rng.uniform(0.01, 0.03)
+            x0, y0 = rng.normal(0, 0.01, 2)
+            for k in range(M):
+                if rng.random() < 0.97:
+                    r = slope * (mz[k] + 600.0)
+                    per[k].append((x0 + r * np.cos(phi) + rng.normal(0, 0.012),
+                                   y0 + r * np.sin(phi) + rng.normal(0, 0.012)))
+        for _ in range(noise):
+            k = int(rng.integers(0, M))
+            r, phi = rng.uniform(5, 40), rng.uniform(-np.pi, np.pi)
+            per[k].append((r * np.cos(phi), r * np.sin(phi)))
+        for k in range(M):
+            rng.shuffle(per[k])
+        xs = np.array([h[0] for p in per for h in p], np.float32)
+        ys = np.array([h[1] for p in per for h in p], np.float32)
+        zs = np.repeat(mz, [len(p) for p in per]).astype(np.float32)
+        events.append(dict(x=xs, y=ys, z=zs, module_counts=np.array([len(p) for p in per], np.int64),
+                           truth=np.full(xs.size, -1, np.int32)))
+    return synth.concat(events, mz)
+
+
+@pytest.mark.parametrize("M", [3, 64])
+def test_fewest_and_most_modules(M):
+    """The module count at both ends of its range (3 and 64 modules)."""
+    say(f"{M} modules")
+    b = _line_events(np.random.default_rng(M), M, 12, 40, 30)
+    want = oracle.reconstruct(b)
+    assert int(want[0][-1]) > 0
+    _same(run_plain(b), want, f"plain M={M}")
+    for tuning in (None, sbt.make_tuning(64, 4, 256), sbt.make_tuning(1024, 1, 1536)):
+        _same(run_batched(b, tuning), want, f"batched M={M} {tuning and tuning.as_dict()}")
+    _same(run_plain(b, reverse=0), oracle.reconstruct(b, reverse=0), f"plain forward M={M}")
