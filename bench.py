@@ -424,6 +424,13 @@ def main():
     extra_streams = [torch.cuda.Stream() for _ in range(3)]
     plain_multi = [plain_streams_leg(torch, sbt, params, batch, args.steps, args.warmup, extra_streams[:t])
                    for t in (2, 3)]
+    # the paper's insertion-rank sort beside the bucket sort (each call: sort kernel + copy-out kernel)
+    sort_ms = {}
+    sort_out = (torch.zeros(H, dtype=torch.int16, device="cuda"), torch.zeros(H, dtype=torch.int16, device="cuda"))
+    for method in ("bucket", "rank"):
+        sec = timed(lambda: sbt.sbt_debug_phi_sort(params, dev, method=method, workspace=ws, out=sort_out,
+                                                   to_host=False), max(5, args.steps // 2), 2)
+        sort_ms[method] = round(sec * 1e3, 4)
 
     # dominant kernel duration: HIP events around the persistent kernel on the
     # stream it is launched on (profiling mode launches without the graph)
@@ -477,6 +484,9 @@ def main():
         "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
                   "hits_per_s": round(H / sec_plain, 1)},
         "plain_streams": plain_multi,
+        "sort_ablation": {"bucket_sort_call_ms": sort_ms["bucket"], "insertion_rank_sort_call_ms": sort_ms["rank"],
+                          "note": "whole batch; each call is the sort kernel, a copy of the sorted angles and ids, "
+                                  "and for the rank sort a host read of the event offsets"},
         "batched_over_plain": round(sec_plain / sec_batched, 3),
         "plain_equals_batched": bool(same_paths),
         "stage_ms": {"k_persistent": round(k_ms, 4), "k_scan": round(float(stage[1]), 4),

@@ -265,6 +265,15 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
                        uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
                        void *stream);
 
+/* The same result from the paper's sort (Section 3, "Sort by phi": a parallel
+ * insertion sort computes the permutation), for comparison with the library's
+ * bucket sort: each hit's rank is the number of hits of its module with a
+ * smaller (phi16, id) key, O(n^2) per module.  Same arguments and errors as
+ * sbt_debug_phi_sort; synchronises `stream` once to size its LDS.          */
+int sbt_debug_phi_sort_rank(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted,
+                            uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
 /* ---- the steps around Search by triplet in the paper's sequence (Section 4) ----------
  *
  * Global event cut: the threshold on the hit count that rejects at most

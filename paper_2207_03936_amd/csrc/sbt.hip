@@ -44,6 +44,43 @@ __global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W
     stage_sort<B>(P, H, event_view(W, e, hb, N), S, sortcap);
 }
 
+// The paper's sort by phi, for comparison (Section 3, "Sort by phi": a
+// parallel insertion sort computes the permutation): every hit counts the
+// hits of its module with a smaller (phi16, id) key, which is its rank,
+// O(n^2) per module.  Keys are in LDS when kLdsKeys, else in the workspace.
+// Writes the same sorted hits as stage_sort.
+template <int B, bool kLdsKeys>
+__global__ __launch_bounds__(B) void k_phi_sort_rank(sbt_params P, HitsArgs H, Work W)
+{
+    __shared__ Shared<B> S;
+    const int e = blockIdx.x;
+    int hb, N;
+    const int st = load_event<B>(P, H, e, S, &hb, &N);
+    if (threadIdx.x == 0) ws_evinfo(W)[e].st = st;
+    if (st != 0) return;
+    const Ev v = event_view(W, e, hb, N);
+    const HitSrc src = hit_src(H, hb);
+    uint32_t *keys = kLdsKeys ? reinterpret_cast<uint32_t *>(g_lds) : v.keys();
+    for (int i = threadIdx.x; i < N; i += B) {
+        float x, y;
+        src.xy(i, x, y);
+        keys[i] = ((uint32_t)phi16(x, y) << 16) | (uint32_t)i;
+    }
+    __syncthreads();
+    const int M = P.n_modules;
+    for (int i = threadIdx.x; i < N; i += B) {
+        const int m = module_of(S.mo, M, i);
+        const int lo = S.mo[m], hi = S.mo[m + 1];
+        const uint32_t key = keys[i];
+        int rank = lo;
+        for (int j = lo; j < hi; ++j) rank += keys[j] < key;
+        Hit16 h;
+        src.xyz(i, h.x, h.y, h.z);
+        h.qid = (key >> 16) | (key << 16);
+        at(v.hs(), rank) = h;
+    }
+}
+
 template <int B, int CAP>
 __global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W, int own_cap)
 {
@@ -621,6 +658,41 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
     const HitsArgs H = hits_args(hits);
     hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, dim3(H.n_events), dim3(kPlainThreads),
                        lds_bytes(kPlainCap, kPlainOwnCap), s, *params, H, W, lds_sortcap(kPlainCap, kPlainOwnCap));
+    hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
+                       phi_sorted, ids_sorted);
+    return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+int sbt_debug_phi_sort_rank(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted,
+                            uint16_t *ids_sorted, void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if ((rc = check_hits(hits))) return rc;
+    if (!phi_sorted || !ids_sorted) return SBT_ERR_INVALID_ARG;
+    if (hits->n_events == 0 || hits->n_hits == 0) return SBT_OK;
+    if (!workspace || ((uintptr_t)workspace & 255)) return SBT_ERR_INVALID_ARG;
+    if (workspace_bytes < carve(hits->n_events, hits->n_hits, nullptr, nullptr)) return SBT_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Work W;
+    carve(hits->n_events, hits->n_hits, (char *)workspace, &W);
+    const HitsArgs H = hits_args(hits);
+    // keys in LDS when the largest event's fit beside the static shared data
+    int max_n = 0;
+    {
+        std::vector<int32_t> eo((size_t)H.n_events + 1);
+        HIP_TRY(hipMemcpyAsync(eo.data(), H.eo, 4 * eo.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t e = 0; e < H.n_events; ++e) max_n = std::max(max_n, eo[(size_t)e + 1] - eo[(size_t)e]);
+    }
+    const size_t lds = 4 * (size_t)max_n;
+    if (lds <= 64 * 1024) {
+        hipLaunchKernelGGL((k_phi_sort_rank<kPlainThreads, true>), dim3(H.n_events), dim3(kPlainThreads), lds, s,
+                           *params, H, W);
+    } else {
+        hipLaunchKernelGGL((k_phi_sort_rank<kPlainThreads, false>), dim3(H.n_events), dim3(kPlainThreads), 0, s,
+                           *params, H, W);
+    }
     hipLaunchKernelGGL(k_copy_sorted, dim3(std::min((H.n_hits + 255) / 256, 4096)), dim3(256), 0, s, H.n_hits, W,
                        phi_sorted, ids_sorted);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;

@@ -126,6 +126,7 @@ PROTOTYPES = {
     "sbt_context_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "sbt_context_stage_ms": (ctypes.c_int, [_VP, _P(ctypes.c_float), ctypes.c_int32]),
     "sbt_debug_phi_sort": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "sbt_debug_phi_sort_rank": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "sbt_server_create": (ctypes.c_int, [_P(SbtParams), _P(SbtTuning), _P(SbtServerConfig), _P(_VP)]),
     "sbt_server_destroy": (None, [_VP]),
     "sbt_server_submit": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_int32),
@@ -330,15 +331,23 @@ def sbt_reconstruct(params: SbtParams, batch: DeviceBatch, out: Optional[DeviceT
     return out
 
 
-def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None):
-    """(phi16, ids) of every hit position after the per-module phi sort."""
+def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None, method: str = "bucket",
+                       workspace: Optional[Workspace] = None, out=None, to_host: bool = True):
+    """(phi16, ids) of every hit position after the per-module phi sort;
+    method "rank" runs the paper's insertion-rank sort instead.  With
+    to_host=False the device tensors are returned without synchronising."""
     torch = _torch()
-    ws = Workspace(batch.n_events, batch.n_hits)
-    phi = torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda")
-    ids = torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda")
-    _check(lib().sbt_debug_phi_sort(ctypes.byref(params), ctypes.byref(batch.hits),
-                                    ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
-                                    ctypes.c_void_p(ws.ptr), ws.bytes, _stream_handle(stream)), "sbt_debug_phi_sort")
+    ws = workspace or Workspace(batch.n_events, batch.n_hits)
+    if out is None:
+        out = (torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda"),
+               torch.zeros(max(batch.n_hits, 1), dtype=torch.int16, device="cuda"))
+    phi, ids = out
+    name = {"bucket": "sbt_debug_phi_sort", "rank": "sbt_debug_phi_sort_rank"}[method]
+    _check(getattr(lib(), name)(ctypes.byref(params), ctypes.byref(batch.hits),
+                                ctypes.c_void_p(phi.data_ptr()), ctypes.c_void_p(ids.data_ptr()),
+                                ctypes.c_void_p(ws.ptr), ws.bytes, _stream_handle(stream)), name)
+    if not to_host:
+        return phi, ids
     n = batch.n_hits
     return (phi[:n].cpu().numpy().view(np.uint16), ids[:n].cpu().numpy().view(np.uint16))
 

@@ -65,11 +65,12 @@ def run_batched(batch, tuning=None, **kw):
 
 # ------------------------------------------------------------------ phi sort
 
+@pytest.mark.parametrize("method", ["bucket", "rank"])
 @pytest.mark.parametrize("config,n", [("tiny", 8), ("mu7.6", 8), ("mu30", 3)])
-def test_phi_sort_matches_oracle(config, n):
-    say(f"phi sort {config} x{n}")
+def test_phi_sort_matches_oracle(config, n, method):
+    say(f"phi sort {config} x{n} ({method})")
     b = synth.make_batch(config, n)
-    phi, ids = sbt.sbt_debug_phi_sort(sbt.make_params(b.module_z), sbt.DeviceBatch(b))
+    phi, ids = sbt.sbt_debug_phi_sort(sbt.make_params(b.module_z), sbt.DeviceBatch(b), method=method)
     M = b.n_modules
     for e in range(b.n_events):
         lo, hi = int(b.event_offsets[e]), int(b.event_offsets[e + 1])
