@@ -103,21 +103,23 @@ def copy_bandwidth(torch, mib=1024, reps=10):
     return 2 * 4 * n / sec / 1e9
 
 
-def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False, streams=None, d2h=False):
+def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False, streams=None, d2h=False, lanes=None):
     """Whole-batch rate with the hits in pinned host memory at the start and
     the tracks in pinned host memory at the end: H2D copies of the inputs,
     then the reconstruction, whose kernels write the tracks straight into
     pinned host buffers (no D2H copy queues in the copy engine behind them).
-    Sequential: everything on one stream.  Pipelined: two contexts on two
-    streams, so the input copy of one batch overlaps the reconstruction of the
-    other.  The two streams should be the same for every pipelined leg: HIP
-    maps streams onto a few hardware queues (four by default), and streams
-    that share one run their work in a single order."""
+    Sequential: everything on one stream.  Pipelined: one context per stream
+    (three by default), so the input copy of one batch overlaps the
+    reconstruction of the others; with two, the streams' copies and kernels
+    sometimes fell into one order and the rate halved.  The streams should be
+    the same for every pipelined leg: HIP maps streams onto a few hardware
+    queues (four by default), and streams that share one run their work in a
+    single order."""
     def pinned(a, dt):
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
     heo, hmo = pinned(batch.event_offsets, np.int32), pinned(batch.module_offsets, np.int32)
     E, H = batch.n_events, batch.n_hits
-    lanes = 2 if pipelined else 1
+    lanes = lanes or (len(streams) if pipelined and streams else (2 if pipelined else 1))
     ctxs = [sbt.Context(params, E, H, tuning) for _ in range(lanes)]
     if f16:
         xyzw = sbt.to_f16_aos(batch.x, batch.y, batch.z)
@@ -168,8 +170,8 @@ def end_to_end(torch, sbt, params, tuning, batch, steps, pipelined, f16=False, s
     out_bytes = 4 * (E + 1) + 4 * (T + 1) + 4 * A + 4 * E
     return dict(events_per_s=round(E / sec, 1), ms_per_step=round(sec * 1e3, 4),
                 pcie_bytes_per_step=int(in_bytes + out_bytes),
-                note=("two contexts on two streams: the input copy of one batch overlaps the reconstruction of "
-                      "the other" if pipelined else "H2D copy and reconstruction on one stream") +
+                note=(f"{lanes} contexts on {lanes} streams: the input copy of one batch overlaps the reconstruction "
+                      "of the others" if pipelined else "H2D copy and reconstruction on one stream") +
                      "; hits in pinned host memory before, tracks written by the kernels into pinned host memory")
 
 
@@ -208,9 +210,9 @@ def sequence_leg(torch, sbt, params, tuning, batch, steps, streams, fraction=0.1
     reconstruction, consolidation.  The cut threshold is calibrated once on
     the batch (the sizes are known before transfer) and applied inside the
     reconstruction; cut events still cross PCIe.  Tracks and consolidated
-    states stay on the device for the algorithms that follow.  Two contexts
-    on two streams, so one batch's input copy overlaps the other's kernels.
-    The rate counts every input event, cut or not."""
+    states stay on the device for the algorithms that follow.  One context per
+    stream, so one batch's input copy overlaps the others' kernels.  The rate
+    counts every input event, cut or not."""
     import ctypes
     E, H = batch.n_events, batch.n_hits
     cut = sbt.sbt_gec_threshold(batch.event_offsets, fraction)
@@ -220,20 +222,21 @@ def sequence_leg(torch, sbt, params, tuning, batch, steps, streams, fraction=0.1
         return torch.from_numpy(np.ascontiguousarray(a, dtype=dt)).pin_memory()
     host = [pinned(batch.x, np.float32), pinned(batch.y, np.float32), pinned(batch.z, np.float32),
             pinned(batch.event_offsets, np.int32), pinned(batch.module_offsets, np.int32)]
-    ctxs = [sbt.Context(p, E, H, tuning) for _ in range(2)]
-    devs = [sbt.DeviceBatch(batch) for _ in range(2)]
-    outs = [sbt.DeviceTracks(E, H) for _ in range(2)]
-    states = [sbt.TrackStates(H) for _ in range(2)]
+    lanes = len(streams)
+    ctxs = [sbt.Context(p, E, H, tuning) for _ in range(lanes)]
+    devs = [sbt.DeviceBatch(batch) for _ in range(lanes)]
+    outs = [sbt.DeviceTracks(E, H) for _ in range(lanes)]
+    states = [sbt.TrackStates(H) for _ in range(lanes)]
 
     def step(k):
-        i = k % 2
+        i = k % lanes
         dev, st = devs[i], streams[i]
         with torch.cuda.stream(st):
             for d, h in zip([dev.x, dev.y, dev.z, dev.eo, dev.mo], host):
                 d.copy_(h, non_blocking=True)
             ctxs[i].reconstruct(dev, outs[i], st)
             sbt.sbt_consolidate(dev, outs[i], states[i], st)
-    for k in range(4):
+    for k in range(2 * lanes):
         step(k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -265,7 +268,7 @@ def sequence_leg(torch, sbt, params, tuning, batch, steps, streams, fraction=0.1
                 cut_hits=int(cut),
                 events_cut=n_cut, n_tracks=int(outs[0].eto[-1].item()),
                 note="global event cut (densest 10 %), H2D copy, reconstruction and consolidation; "
-                     "results stay on the device; two contexts on two streams; no decoding step")
+                     f"results stay on the device; {lanes} contexts on {lanes} streams; no decoding step")
 
 
 def _oracle_slice(args):
@@ -450,7 +453,7 @@ def main():
     sq = measured_sq(H)
     if not args.no_e2e:
         e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
-        pipe_streams = extra_streams[:2]
+        pipe_streams = extra_streams
         e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
                            streams=pipe_streams)
     # half-precision array-of-structures input (the paper's hit-storage optimisation)
