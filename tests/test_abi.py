@@ -38,7 +38,7 @@ def test_params_validation():
     p = sbt.make_params(synth.PLANE_Z)
     assert L.sbt_params_validate(ctypes.byref(p)) == 0
     bad = [dict(max_doublet_candidates=0), dict(phi_window_seeding=32768), dict(phi_window_forwarding=-1),
-           dict(max_consecutive_misses=-1), dict(reverse=2)]
+           dict(max_consecutive_misses=-1), dict(reverse=2), dict(max_event_hits=-1)]
     for b in bad:
         assert L.sbt_params_validate(ctypes.byref(sbt.make_params(synth.PLANE_Z, **b))) == sbt.SBT_ERR_INVALID_ARG
     assert L.sbt_params_validate(ctypes.byref(sbt.make_params(synth.PLANE_Z[:2]))) == sbt.SBT_ERR_INVALID_ARG

@@ -236,6 +236,29 @@ def test_bad_offsets_are_reported():
         assert list(np.delete(np.diff(got[0]), 1)) == list(np.diff(want[0]))
 
 
+def test_capacity_errors_are_reported():
+    """A context smaller than the batch and a short workspace are refused
+    before any launch."""
+    say("capacity errors")
+    b = synth.make_batch("tiny", 4)
+    p = sbt.make_params(b.module_z)
+    dev = sbt.DeviceBatch(b)
+    ctx = sbt.Context(p, b.n_events - 1, b.n_hits)
+    with pytest.raises(sbt.SbtError) as ei:
+        ctx.reconstruct(dev)
+    assert ei.value.code == sbt.SBT_ERR_WORKSPACE
+    ctx.close()
+    ctx = sbt.Context(p, b.n_events, b.n_hits - 1)
+    with pytest.raises(sbt.SbtError) as ei:
+        ctx.reconstruct(dev)
+    assert ei.value.code == sbt.SBT_ERR_WORKSPACE
+    ctx.close()
+    ws = sbt.Workspace(b.n_events, b.n_hits // 4)
+    with pytest.raises(sbt.SbtError) as ei:
+        sbt.sbt_reconstruct(p, dev, workspace=ws)
+    assert ei.value.code == sbt.SBT_ERR_WORKSPACE
+
+
 # ------------------------------------------------------------------ full sizes
 
 def _invariants(b, got):
