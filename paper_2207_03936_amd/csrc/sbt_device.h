@@ -408,6 +408,8 @@ __device__ __forceinline__ int lane_xor(int v, int m)
 //   res    per active slot: the search result (best hit id | window position
 //          << 16, scatter) and the claim set's inputs (key, seed hits)
 //   cfree  unflagged-position bits of the seeding stage's third module
+//   lclaim claim words of the module being searched by the following
+//          stage, by window position (the claims on seed hits stay in memory)
 //   own    hit-flag bitmap of the event when N <= own_cap
 extern __shared__ __align__(16) char g_lds[];
 
@@ -422,7 +424,8 @@ __host__ __device__ constexpr uint32_t lay_al0(int cap) { return lay_frank(cap) 
 __host__ __device__ constexpr uint32_t lay_al1(int cap) { return lay_al0(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_res(int cap) { return lay_al1(cap) + a16(2u * cap); }
 __host__ __device__ constexpr uint32_t lay_cfree(int cap) { return lay_res(cap) + 16u * cap; }
-__host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_cfree(cap) + a16(8u * (uint32_t)((cap + 63) / 64)); }
+__host__ __device__ constexpr uint32_t lay_lclaim(int cap) { return lay_cfree(cap) + a16(8u * (uint32_t)((cap + 63) / 64)); }
+__host__ __device__ constexpr uint32_t lay_own(int cap) { return lay_lclaim(cap) + 8u * (uint32_t)cap; }
 
 // sort bins: 1024 in total, a power of two per module
 constexpr int kSortBins = 1024;
@@ -465,6 +468,10 @@ struct Lay {
     static __device__ __forceinline__ unsigned long long *cfree()
     {
         return reinterpret_cast<unsigned long long *>(g_lds + lay_cfree(CAP));
+    }
+    static __device__ __forceinline__ unsigned long long *lclaim()
+    {
+        return reinterpret_cast<unsigned long long *>(g_lds + lay_lclaim(CAP));
     }
 };
 
@@ -963,7 +970,8 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
 // Returns the best hit's id | window position << 16, or ~0.
 template <bool kLds>
 __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, float Zc, const uint32_t *own,
-                                                unsigned long long *claim, const Rec &R, int u, float &bsc_out)
+                                                unsigned long long *claim, unsigned long long *lclaim, const Rec &R,
+                                                int u, float &bsc_out)
 {
     const float Sf = P.Sf;
     const uint16_t Wf = (uint16_t)P.Wf;
@@ -1007,7 +1015,8 @@ __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, flo
         }
         if (best != kNone) {
             const unsigned long long kap = claim_key(bsc, R.key, u);
-            atomicMin(&at(claim, best), kap);
+            if (kLds) atomicMin(&lclaim[bpos], kap);
+            else atomicMin(&at(claim, best), kap);
             if (R.len == 3) {
                 atomicMin(&at(claim, R.h0), kap);
                 atomicMin(&at(claim, R.h1), kap);
@@ -1088,6 +1097,9 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
     int nmax = na > nbm ? na : nbm;
     if (kLds && wc.n > nmax) nmax = wc.n;
     unsigned long long *cfree = kLds ? Lay<CAP>::cfree() : nullptr;
+    unsigned long long *lclaim = kLds ? Lay<CAP>::lclaim() : nullptr;
+    if (kLds && follow_next)
+        for (int p = threadIdx.x; p < wn.n; p += B) lclaim[p] = kNoClaim;
     int phase = 0;
     for (int base = 0; base < nmax; base += B, ++phase) {
         const int p = base + (int)threadIdx.x;
@@ -1125,7 +1137,7 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
                 const int r = at(nxt, a);
                 const Rec R = at(v.rec(), r);
                 float bsc;
-                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
+                const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), lclaim, R, t + 1, bsc);
                 put_result<kLds, CAP>(v, a, r, pb, bsc, R);
             }
             continue;
@@ -1197,7 +1209,7 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
                 at(nxt, l) = (uint16_t)r;
                 if (follow_next) {
                     float bsc;
-                    const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), R, t + 1, bsc);
+                    const uint32_t pb = follow_item<kLds>(P, wn, Zn, own, v.claim(), lclaim, R, t + 1, bsc);
                     put_result<kLds, CAP>(v, l, r, pb, bsc, R);
                 }
             }
@@ -1248,7 +1260,7 @@ __device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, 
                 const uint16_t best = (uint16_t)(pb & 0xFFFF);
                 const unsigned long long kap = claim_key(bsc, (uint16_t)(k0 & 0xFFFFu), t);
                 const uint16_t h0 = (uint16_t)(k0 >> 16);
-                win = at(claim, best) == kap;
+                win = kLds ? Lay<CAP>::lclaim()[pb >> 16] == kap : at(claim, best) == kap;
                 if (h0 != kNone)
                     win = win && at(claim, h0) == kap && at(claim, (uint16_t)(k12 & 0xFFFFu)) == kap &&
                           at(claim, (uint16_t)(k12 >> 16)) == kap;
