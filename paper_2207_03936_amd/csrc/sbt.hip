@@ -192,8 +192,25 @@ __global__ __launch_bounds__(kWriteThreads) void k_write(HitsArgs H, Work W, Out
         if (nt == 0) continue;
         const int hb = H.eo[e];
         const int t0 = ws_evinfo(W)[e].out_t, p0 = ws_evinfo(W)[e].out_h;
-        for (int i = threadIdx.x; i < nt; i += kWriteThreads) O.tho[t0 + i] = p0 + ws_toff(W)[hb + i];
-        for (int j = threadIdx.x; j < nh; j += kWriteThreads) O.th[p0 + j] = ws_sthits(W)[hb + j];
+        // four elements per lane and pass, their loads in flight together
+        for (int i0 = threadIdx.x; i0 < nt; i0 += 4 * kWriteThreads) {
+            int v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k * kWriteThreads < nt) v[k] = ws_toff(W)[hb + i0 + k * kWriteThreads];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (i0 + k * kWriteThreads < nt) O.tho[t0 + i0 + k * kWriteThreads] = p0 + v[k];
+        }
+        for (int j0 = threadIdx.x; j0 < nh; j0 += 4 * kWriteThreads) {
+            int v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j0 + k * kWriteThreads < nh) v[k] = ws_sthits(W)[hb + j0 + k * kWriteThreads];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j0 + k * kWriteThreads < nh) O.th[p0 + j0 + k * kWriteThreads] = v[k];
+        }
     }
 }
 
@@ -211,7 +228,16 @@ __global__ __launch_bounds__(kWriteThreads) void k_write_events(HitsArgs H, Work
         const int hb = H.eo[e];
         int32_t *tho = O.tho + I.out_t + e;
         for (int i = threadIdx.x; i <= I.nt; i += kWriteThreads) tho[i] = i < I.nt ? ws_toff(W)[hb + i] : I.nh;
-        for (int j = threadIdx.x; j < I.nh; j += kWriteThreads) O.th[I.out_h + j] = ws_sthits(W)[hb + j];
+        // four hit ids per lane and pass, their loads in flight together
+        for (int j0 = threadIdx.x; j0 < I.nh; j0 += 4 * kWriteThreads) {
+            int v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j0 + k * kWriteThreads < I.nh) v[k] = ws_sthits(W)[hb + j0 + k * kWriteThreads];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (j0 + k * kWriteThreads < I.nh) O.th[I.out_h + j0 + k * kWriteThreads] = v[k];
+        }
     }
 }
 
