@@ -11,7 +11,9 @@
 //   owner   one bit per hit id: set once a track has taken the hit (the
 //           method only ever asks whether a hit is flagged; which track
 //           holds it is settled by the claim keys)
-//   claim   u64 per hit id: minimum claim key of the current stage
+//   claim   u64 per hit id: minimum claim key of the current stage (the LDS
+//           instantiation keeps the claims on followers' best hits in LDS,
+//           by window position, and only the seed hits' claims here)
 //   link    two u16 per hit id: the previous hit of the owning track, and
 //           the record of the accepted track whose key is this id
 //   rec     32-byte forming-track records (one per seed; <= N) and a 16-byte
@@ -966,8 +968,10 @@ __device__ __forceinline__ void seed_doublet(const Win &wa, const Win &wc, const
 // "track following"): the last two hits extrapolated to the module's
 // nominal z, the best unflagged hit of the inclusive phi window by
 // (scatter, id) under the threshold, and claims on that hit (and on the
-// three seed hits of a bare seed) keyed (scatter, key) for stage u.
-// Returns the best hit's id | window position << 16, or ~0.
+// three seed hits of a bare seed) keyed (scatter, key) for stage u.  The LDS
+// instantiation claims the best hit in lclaim, by window position; seed
+// hits are always claimed in memory.  Returns the best hit's id | window
+// position << 16, or ~0.
 template <bool kLds>
 __device__ __forceinline__ uint32_t follow_item(const Prm &P, const Win &wc, float Zc, const uint32_t *own,
                                                 unsigned long long *claim, unsigned long long *lclaim, const Rec &R,
