@@ -374,6 +374,20 @@ def test_full_size_all_events(config, n, tuning):
     assert not got[3].any()
     _same(got, want, f"{config} x{n} {tuning}")
     _invariants(b, got)
+    if tuning == (512, 2, 672):
+        say("  plain form")
+        _same(run_plain(b), want, f"plain {config} x{n}")
+
+
+def test_full_size_half_precision():
+    """The binary16 entry point on the full mu in U{1..25} batch: every event
+    against the oracle on the rounded coordinates."""
+    say("full mu1-25 x10000, binary16 input")
+    b = rounded_to_f16(synth.make_batch("mu1-25", 10000))
+    want = oracle.reconstruct(b)
+    got = run_batched_f16(b, sbt.make_tuning(512, 2, 672))
+    assert not got[3].any()
+    _same(got, want, "f16 mu1-25 x10000")
 
 
 def test_repeat_runs_identical():
