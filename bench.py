@@ -5,9 +5,14 @@ vertices, Poisson(40) tracks each, 26 planes), synthetic and seeded.  A step
 is one pass of the whole hot path (phi sort, seeding and following, tracklet
 filter, compaction) over the batch, with inputs and outputs resident in HBM.
 `value` is the batched path (persistent kernel + captured graph); the plain
-per-event kernels are timed beside it.  A short serving leg reports p50/p99
-event latency under continuous batching, and the CPU oracle is timed on a
-bounded sample of the same events.
+per-event kernels are timed beside it, on one stream and on 2 and 3 streams
+over slices of the batch.  Further legs, each reported apart from `value`:
+the insertion-rank sort beside the bucket sort; binary16 input; end to end
+from pinned host memory (one stream, then three); the paper's sequence
+around the method (event cut, transfer, reconstruction, consolidation); a
+short serving leg with p50/p99 event latency under continuous batching; and
+the CPU oracle on a bounded sample of the same events, on one core and on
+all of them.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
