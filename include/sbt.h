@@ -339,6 +339,11 @@ typedef struct sbt_server_result {
     double t_done_us;            /* when the result was visible on the host        */
 } sbt_server_result;
 
+/* tuning: the launch configuration of every slot, or NULL to choose it per
+ * launch from the slot's shape: 1,024 lanes per event (one workgroup per
+ * compute unit, 1,536-hit LDS slots) when the slot holds at most one event
+ * per compute unit, or at most two of 4,000 hits or more on average; the
+ * library default otherwise.  Results never depend on it.                */
 int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning,
                       const sbt_server_config *config, sbt_server **out);
 void sbt_server_destroy(sbt_server *srv);

@@ -183,6 +183,8 @@ struct ReadyResult {
 struct sbt_server {
     sbt_params params;
     sbt_tuning tuning;
+    bool per_launch_tuning;  // no tuning given: chosen per launch from the slot's shape
+    int cus;                 // compute units of the device
     sbt_server_config cfg;
     std::vector<Slot> slots;
     std::deque<QueuedEvent> queue;
@@ -304,6 +306,23 @@ void pack(sbt_server *srv, Slot &s, QueuedEvent &q)
     s.events.push_back(std::move(se));
 }
 
+// Launch configuration of a slot when the caller gave none.  A slot that
+// gives each compute unit at most one event, or at most two large ones,
+// runs 1,024 lanes per event (one workgroup per CU, 1,536-hit LDS slots):
+// each event finishes sooner, which is what a lightly loaded server needs.
+// Fuller slots run the library's default, built for throughput.
+sbt_tuning launch_tuning(const sbt_server *srv, int E, int H)
+{
+    if (!srv->per_launch_tuning) return srv->tuning;
+    const bool wide = E <= srv->cus || (E <= 2 * srv->cus && (long long)H >= 4000LL * E);
+    if (!wide) return srv->tuning;
+    sbt_tuning t = srv->tuning;
+    t.threads_per_event = 1024;
+    t.blocks_per_cu = 1;
+    t.lds_window_hits = 1536;
+    return t;
+}
+
 int launch(sbt_server *srv, Slot &s)
 {
     const int M = srv->params.n_modules;
@@ -342,7 +361,7 @@ int launch(sbt_server *srv, Slot &s)
     out.hoff = block->hoff;
     out.tho = block->tho;
     out.th = block->th;
-    int rc = sbt::launch_batched_events(srv->params, srv->tuning, hits, out, s.dwork, st);
+    int rc = sbt::launch_batched_events(srv->params, launch_tuning(srv, (int)E, (int)H), hits, out, s.dwork, st);
     if (rc) return rc;
     if (hipEventRecord(s.done, st) != hipSuccess) return SBT_ERR_HIP;
     s.block = std::move(block);
@@ -449,6 +468,16 @@ int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const 
     if (!srv) return SBT_ERR_NOMEM;
     srv->params = *params;
     srv->tuning = t;
+    srv->per_launch_tuning = tuning == nullptr;
+    {
+        int dev = 0;
+        srv->cus = 256;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&srv->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            delete srv;
+            return SBT_ERR_HIP;
+        }
+    }
     srv->cfg = c;
     srv->max_queue = (size_t)c.n_slots * (size_t)c.slot_events * 4;
     srv->open_slot = -1;
