@@ -178,7 +178,9 @@ typedef struct sbt_tracks {
  * blocks_per_cu       persistent workgroups per compute unit (1..16).
  * lds_window_hits     capacity, in hits, of each of the four LDS slots that
  *                     hold the phi-sorted hits of consecutive modules
- *                     (0..2048); a larger module is read from memory.
+ *                     (0..2048), rounded down to a compiled one (0, 256,
+ *                     448, 672, 768, 1024, 1536); an event with a larger
+ *                     module reads all its modules from memory.
  * lds_owner_hits      events with at most this many hits keep their hit
  *                     flags (one bit per hit) in LDS, larger ones in
  *                     memory (0..65536).
@@ -223,7 +225,17 @@ int sbt_reconstruct(const sbt_params *params, const sbt_hits *hits, sbt_tracks *
  * its workspace only if the caller orders them).                         */
 typedef struct sbt_context sbt_context;
 
-/* tuning NULL selects the library default for the current device. */
+/* tuning: the launch configuration of every call, or NULL to choose it per
+ * call from the batch's size on the current device: 1,024 lanes per event,
+ * one workgroup per compute unit and 1,536-hit LDS slots for a batch of at
+ * most one event per compute unit, or at most two of 4,000 hits or more on
+ * average; otherwise 512 lanes, two workgroups per compute unit, and 768-hit
+ * slots for events of 4,000 hits or more on average, 672-hit slots for
+ * smaller ones (lds_owner_hits 16,384 throughout).  sbt_context_set_tuning
+ * and sbt_autotune install one configuration for every later call;
+ * sbt_context_get_tuning reports the installed one, or without one the
+ * choice for a batch of max_events events and max_hits hits.  Results never
+ * depend on the configuration.                                           */
 int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning,
                        int32_t max_events, int32_t max_hits, sbt_context **out);
 void sbt_context_destroy(sbt_context *ctx);
@@ -340,10 +352,10 @@ typedef struct sbt_server_result {
 } sbt_server_result;
 
 /* tuning: the launch configuration of every slot, or NULL to choose it per
- * launch from the slot's shape: 1,024 lanes per event (one workgroup per
- * compute unit, 1,536-hit LDS slots) when the slot holds at most one event
- * per compute unit, or at most two of 4,000 hits or more on average; the
- * library default otherwise.  Results never depend on it.                */
+ * launch from the slot's size by the rule sbt_context_create describes
+ * (slots of at most one event per compute unit, or two large ones, run
+ * 1,024 lanes per event, each event then finishing sooner).  Results never
+ * depend on it.                                                          */
 int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning,
                       const sbt_server_config *config, sbt_server **out);
 void sbt_server_destroy(sbt_server *srv);

@@ -780,6 +780,8 @@ struct sbt_context {
     int profiling;
     hipEvent_t marks[4];
     int have_marks;
+    int per_launch;   // created without a tuning: chosen per call from the batch's size
+    int cus;          // compute units of the device the context was created on
 };
 
 namespace {
@@ -812,6 +814,28 @@ sbt_tuning default_tuning()
     return t;
 }
 
+// Launch configuration for a batch of E events and H hits on a device of
+// `cus` compute units.  A batch of at most one event per compute unit, or at
+// most two large ones (4,000 hits or more on average), runs 1,024 lanes per
+// event, one workgroup per CU with 1,536-hit slots: each event then finishes
+// sooner, and there are too few events to fill the device twice.  Larger
+// batches run 512 lanes, two workgroups per CU; batches of large events take
+// 768-hit slots (the largest that still fit two workgroups' LDS on a CU), so
+// that their busiest modules stay in LDS rather than in memory.
+sbt_tuning size_tuning(int E, int H, int cus)
+{
+    sbt_tuning t = default_tuning();
+    const bool large = (long long)H >= 4000LL * E;
+    if (E <= cus || (E <= 2 * cus && large)) {
+        t.threads_per_event = 1024;
+        t.blocks_per_cu = 1;
+        t.lds_window_hits = 1536;
+    } else if (large) {
+        t.lds_window_hits = 768;
+    }
+    return t;
+}
+
 }  // namespace
 
 extern "C" {
@@ -834,6 +858,15 @@ int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning, int32
     c->clock = 0;
     c->profiling = 0;
     c->have_marks = 0;
+    c->per_launch = tuning == nullptr;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            delete c;
+            return SBT_ERR_HIP;
+        }
+    }
     if (hipMalloc(&c->workspace, c->workspace_bytes) != hipSuccess) {
         delete c;
         return SBT_ERR_NOMEM;
@@ -866,8 +899,9 @@ int sbt_context_set_tuning(sbt_context *c, const sbt_tuning *t)
     if (!c || !t) return SBT_ERR_INVALID_ARG;
     int rc = valid_tuning(*t);
     if (rc) return rc;
-    if (memcmp(&c->tuning, t, sizeof *t) != 0) {
+    if (c->per_launch || memcmp(&c->tuning, t, sizeof *t) != 0) {
         c->tuning = *t;
+        c->per_launch = 0;
         drop_graphs(c);
     }
     return SBT_OK;
@@ -876,7 +910,7 @@ int sbt_context_set_tuning(sbt_context *c, const sbt_tuning *t)
 int sbt_context_get_tuning(const sbt_context *c, sbt_tuning *out)
 {
     if (!c || !out) return SBT_ERR_INVALID_ARG;
-    *out = c->tuning;
+    *out = c->per_launch ? size_tuning(c->max_events, c->max_hits, c->cus) : c->tuning;
     return SBT_OK;
 }
 
@@ -911,8 +945,9 @@ int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
         hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
         return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
     }
+    const sbt_tuning T = c->per_launch ? size_tuning(H.n_events, H.n_hits, c->cus) : c->tuning;
     if (c->profiling || s == nullptr) {
-        rc = launch_batched(c->params, c->tuning, H, c->W, O, s, c->profiling ? c->marks : nullptr);
+        rc = launch_batched(c->params, T, H, c->W, O, s, c->profiling ? c->marks : nullptr);
         if (rc == SBT_OK && c->profiling) c->have_marks = 1;
         return rc;
     }
@@ -930,7 +965,7 @@ int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
     }
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    rc = launch_batched(c->params, c->tuning, H, c->W, O, s, nullptr);
+    rc = launch_batched(c->params, T, H, c->W, O, s, nullptr);
     hipError_t ec = hipStreamEndCapture(s, &graph);
     if (rc != SBT_OK || ec != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -991,7 +1026,7 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
     // candidates: lanes per event x LDS slot capacity, each at the largest
     // number of resident workgroups per CU and one less
     const int tpes[] = {128, 256, 512, 1024};
-    const int caps[] = {256, 448, 672, 1024, 1536};
+    const int caps[] = {256, 448, 672, 768, 1024, 1536};
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;
     rc = SBT_OK;
@@ -1078,6 +1113,7 @@ int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, co
 }
 
 sbt_tuning default_tuning_config() { return default_tuning(); }
+sbt_tuning batch_tuning(int32_t E, int32_t H, int cus) { return size_tuning(E, H, cus); }
 int tuning_valid(const sbt_tuning &t) { return valid_tuning(t); }
 
 }  // namespace sbt

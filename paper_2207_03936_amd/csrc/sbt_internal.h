@@ -32,8 +32,10 @@ struct EventOut {
 int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
                           const EventOut &out, void *workspace, hipStream_t stream);
 
-// The library's default launch configuration.
+// The library's default launch configuration, and the one it chooses for a
+// batch of E events and H hits on a device of `cus` compute units.
 sbt_tuning default_tuning_config();
+sbt_tuning batch_tuning(int32_t E, int32_t H, int cus);
 int tuning_valid(const sbt_tuning &t);
 
 }  // namespace sbt

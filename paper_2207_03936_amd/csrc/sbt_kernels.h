@@ -6,8 +6,8 @@ namespace sbt {
 
 // LDS slot capacities with a compiled persistent kernel (0: every event reads
 // its modules from memory); a requested capacity is rounded down to one.
-constexpr int kCaps[] = {0, 256, 448, 672, 1024, 1536};
-constexpr int kNumCaps = 6;
+constexpr int kCaps[] = {0, 256, 448, 672, 768, 1024, 1536};
+constexpr int kNumCaps = 7;
 
 // host stub of the persistent kernel of width tpe for an instantiated
 // capacity, or nullptr

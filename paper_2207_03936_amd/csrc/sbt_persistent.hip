@@ -62,6 +62,7 @@ const void *SBT_CAT(persistent_kernel_, SBT_TPE)(int cap)
     case 256: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 256>);
     case 448: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 448>);
     case 672: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 672>);
+    case 768: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 768>);
     case 1024: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 1024>);
     case 1536: return reinterpret_cast<const void *>(k_persistent<SBT_TPE, 1536>);
     default: return nullptr;

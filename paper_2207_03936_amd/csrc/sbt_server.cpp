@@ -306,21 +306,13 @@ void pack(sbt_server *srv, Slot &s, QueuedEvent &q)
     s.events.push_back(std::move(se));
 }
 
-// Launch configuration of a slot when the caller gave none.  A slot that
-// gives each compute unit at most one event, or at most two large ones,
-// runs 1,024 lanes per event (one workgroup per CU, 1,536-hit LDS slots):
-// each event finishes sooner, which is what a lightly loaded server needs.
-// Fuller slots run the library's default, built for throughput.
+// Launch configuration of a slot: the caller's, or when none was given the
+// library's choice for the slot's size (at most one event per compute unit,
+// or two large ones, run 1,024 lanes per event, so that each finishes sooner,
+// which is what a lightly loaded server needs).
 sbt_tuning launch_tuning(const sbt_server *srv, int E, int H)
 {
-    if (!srv->per_launch_tuning) return srv->tuning;
-    const bool wide = E <= srv->cus || (E <= 2 * srv->cus && (long long)H >= 4000LL * E);
-    if (!wide) return srv->tuning;
-    sbt_tuning t = srv->tuning;
-    t.threads_per_event = 1024;
-    t.blocks_per_cu = 1;
-    t.lds_window_hits = 1536;
-    return t;
+    return srv->per_launch_tuning ? sbt::batch_tuning(E, H, srv->cus) : srv->tuning;
 }
 
 int launch(sbt_server *srv, Slot &s)

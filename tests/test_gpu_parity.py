@@ -121,7 +121,7 @@ def test_batched_independent_of_launch_configuration(tpe, bpc):
 # LDS capacities: 0 or 1 forces every module window / the owner flags to be
 # read from memory, intermediate values mix both within one event
 LDS_CASES = [(0, 0), (1, 1), (64, 1000), (200, 3000), (256, 16384), (448, 16384), (672, 16384),
-             (1024, 65536), (1536, 0)]
+             (768, 16384), (1024, 65536), (1536, 0)]
 
 
 @pytest.mark.parametrize("cap,own", LDS_CASES)
@@ -364,6 +364,7 @@ def _full_batch(config, n):
 # full batches in the launch configurations the autotuner picks for them:
 # every event against the oracle
 @pytest.mark.parametrize("config,n,tuning", [("mu1-25", 10000, (512, 2, 672)),
+                                             ("mu1-25", 10000, (512, 2, 768)),
                                              ("mu30", 2000, (1024, 1, 1536)),
                                              ("mu30", 2000, (512, 2, 672))])
 def test_full_size_all_events(config, n, tuning):
@@ -388,6 +389,38 @@ def test_full_size_half_precision():
     got = run_batched_f16(b, sbt.make_tuning(512, 2, 672))
     assert not got[3].any()
     _same(got, want, "f16 mu1-25 x10000")
+
+
+def _expected_choice(n_events, n_hits, cus):
+    large = n_hits >= 4000 * n_events
+    if n_events <= cus or (n_events <= 2 * cus and large):
+        return (1024, 1, 1536)
+    return (512, 2, 768 if large else 672)
+
+
+@pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000)])
+def test_configuration_chosen_per_call(config, n):
+    """A context created without a launch configuration chooses one per call
+    from the batch's size.  Each choice, a smaller batch through the same
+    context and an installed configuration all give the oracle's tracks."""
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    say(f"per-call configuration {config} x{n} ({cus} CUs)")
+    b = synth.make_batch(config, n)
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    t = ctx.get_tuning()
+    assert (t.threads_per_event, t.blocks_per_cu, t.lds_window_hits) == _expected_choice(n, b.n_hits, cus)
+    assert t.lds_owner_hits == 16384
+    want = oracle.reconstruct(b)
+    _same(ctx.reconstruct(sbt.DeviceBatch(b)).to_host(), want, f"{config} x{n} per call")
+    small = synth.make_batch(config, 20, first=5)
+    _same(ctx.reconstruct(sbt.DeviceBatch(small)).to_host(), oracle.reconstruct(small), "smaller batch")
+    ctx.set_tuning(sbt.make_tuning(256, 4, 448))
+    t = ctx.get_tuning()
+    assert (t.threads_per_event, t.blocks_per_cu, t.lds_window_hits) == (256, 4, 448)
+    _same(ctx.reconstruct(sbt.DeviceBatch(b)).to_host(), want, f"{config} x{n} installed")
+    ctx.close()
 
 
 def test_repeat_runs_identical():
