@@ -1437,22 +1437,107 @@ __device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, cons
 }
 
 // ---------------------------------------------------------------- per-event compaction
-// Accepted tracks in key order: per-event track offsets and hit ids into the
-// staging arrays, counts into the event's counters.
-template <int B>
-__device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
+// The accepted tracks in key order (the id of the seed's middle hit), each as
+// its three seed hits followed by the hits appended to it in traversal order:
+// per-event track offsets and hit ids into the staging arrays, counts into
+// the event's counters.
+constexpr int kCompactBatch = 8;   // key rounds whose link loads are in flight together
+
+// Whether the LDS form of the compaction fits: the previous-hit links (2 B
+// per hit) and the record of each accepted track in key order (2 B per
+// track; tracks are disjoint with at least three hits, so at most N / 3).
+__host__ __device__ inline bool compact_fits_lds(int N, int lds_bytes)
 {
-    const Ev v = fresh(v0);
+    return (int)a16(2u * (uint32_t)N) + 2 * (N / 3 + 1) <= lds_bytes;
+}
+
+// LDS form.  Pass 1 takes the keys in rounds of B (key = round * B + lane,
+// loads coalesced, kCompactBatch rounds in flight), copies each previous-hit
+// link to LDS and ranks the keys that own a record with a ballot count over
+// the workgroup, which lists the records in key order.  Pass 2 gives each
+// listed track a lane: an exclusive scan of the lengths places its hits, and
+// the lane writes them, walking the links in LDS.
+template <int B>
+__device__ void compact_lds(const Ev &v, int *s_scan, int lds_bytes)
+{
     const int N = v.N;
-    // the previous-hit links in LDS (free after the tracking stages) when
-    // they fit, so that the chain walk below costs LDS latency per hop
     uint16_t *lprev = reinterpret_cast<uint16_t *>(g_lds);
-    const bool in_lds = 2 * N <= lds_bytes;
-    if (in_lds) {
-        for (int i = threadIdx.x; i < N; i += B) lprev[i] = at(v.link(), 2u * i);
+    uint16_t *lrec = reinterpret_cast<uint16_t *>(g_lds + a16(2u * (uint32_t)N));
+    const int rec_cap = (lds_bytes - (int)a16(2u * (uint32_t)N)) / 2;
+    const uint32_t *link = reinterpret_cast<const uint32_t *>(v.link());   // prev | record << 16
+    const int rounds = (N + B - 1) / B;
+    bool bad = false;
+    int nt = 0;
+    for (int j0 = 0; j0 < rounds; j0 += kCompactBatch) {
+        uint32_t w[kCompactBatch];
+#pragma unroll
+        for (int u = 0; u < kCompactBatch; ++u) {
+            const int k = (j0 + u) * B + (int)threadIdx.x;
+            w[u] = k < N ? at(link, (uint32_t)k) : ((uint32_t)kNone << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < kCompactBatch; ++u) {
+            if (j0 + u >= rounds) break;
+            const int k = (j0 + u) * B + (int)threadIdx.x;
+            const uint16_t r = (uint16_t)(w[u] >> 16);
+            if (k < N) lprev[k] = (uint16_t)(w[u] & 0xFFFFu);
+            int tot;
+            const int pos = nt + (block_count2<B>(r != kNone, false, s_scan, j0 + u, &tot) & 0xFFFF);
+            if (r != kNone) {
+                if (pos < rec_cap) lrec[pos] = r;
+                else bad = true;
+            }
+            nt += tot & 0xFFFF;
+        }
     }
-    // each lane owns a contiguous range of keys: count its tracks and hits,
-    // one scan of each over the workgroup, then write them in key order
+    __syncthreads();   // links and the record list visible
+    if (nt > rec_cap) nt = 0;
+    int nh = 0;
+    for (int t0 = 0; t0 < nt; t0 += B) {
+        const int t = t0 + (int)threadIdx.x;
+        Rec R;
+        int len = 0;
+        if (t < nt) {
+            R = at(v.rec(), lrec[t]);
+            len = R.len;
+        }
+        int tot;
+        const int hi = nh + block_excl_scan<B>(len, s_scan, t0 / B, &tot);
+        nh += tot;
+        if (t < nt) {
+            // tracks are disjoint, so hi + len <= N; the checks below only
+            // keep a broken invariant from turning into a stray access
+            if (hi + len > N) {
+                bad = true;
+            } else {
+                at(v.st_toff(), t) = hi;
+                uint16_t *out = v.st_hits() + hi;
+                uint16_t p = R.last;
+                for (int j = len - 1; j >= 3; --j) {
+                    if (p >= N) { bad = true; break; }
+                    out[j] = p;
+                    p = lprev[p];
+                }
+                out[2] = R.h2;
+                out[1] = R.h1;
+                out[0] = R.h0;
+            }
+        }
+    }
+    if (bad) v.info().st = (int)SBT_EV_INTERNAL;
+    if (threadIdx.x == 0) {
+        v.info().nt = nh <= N ? nt : 0;
+        v.info().nh = nh <= N ? nh : 0;
+    }
+}
+
+// Memory form (events whose links do not fit, and the plain kernel): each
+// lane owns a contiguous range of keys; it counts their tracks and hits, one
+// scan of each over the workgroup, then it writes them in key order.
+template <int B>
+__device__ void compact_mem(const Ev &v, int *s_scan)
+{
+    const int N = v.N;
     const int per = (N + B - 1) / B;
     const int k0 = min(N, (int)threadIdx.x * per), k1 = min(N, k0 + per);
     int nt = 0, nh = 0;
@@ -1466,14 +1551,11 @@ __device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
     int tt, th;
     int ti = block_excl_scan<B>(nt, s_scan, 0, &tt);
     int hi = block_excl_scan<B>(nh, s_scan, 1, &th);
-    __syncthreads();   // LDS links visible
     bool bad = th > N;
     for (int k = k0; k < k1 && !bad; ++k) {
         const uint16_t r = at(v.link(), 2u * k + 1u);
         if (r == kNone) continue;
         const Rec R = at(v.rec(), r);
-        // tracks are disjoint, so hi + len <= N; the checks below only keep a
-        // broken invariant from turning into a stray access
         if (hi + R.len > N) {
             bad = true;
             break;
@@ -1481,18 +1563,10 @@ __device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
         at(v.st_toff(), ti) = hi;
         uint16_t *out = v.st_hits() + hi;
         uint16_t p = R.last;
-        if (in_lds) {
-            for (int j = R.len - 1; j >= 3; --j) {
-                if (p >= N) { bad = true; break; }
-                out[j] = p;
-                p = lprev[p];
-            }
-        } else {
-            for (int j = R.len - 1; j >= 3; --j) {
-                if (p >= N) { bad = true; break; }
-                out[j] = p;
-                p = at(v.link(), 2u * p);
-            }
+        for (int j = R.len - 1; j >= 3; --j) {
+            if (p >= N) { bad = true; break; }
+            out[j] = p;
+            p = at(v.link(), 2u * p);
         }
         out[2] = R.h2;
         out[1] = R.h1;
@@ -1505,6 +1579,15 @@ __device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
         v.info().nt = th <= N ? tt : 0;
         v.info().nh = th <= N ? th : 0;
     }
+}
+
+// lds_bytes: LDS free for the compaction (0: none)
+template <int B>
+__device__ void stage_compact(const Ev &v0, int *s_scan, int lds_bytes)
+{
+    const Ev v = fresh(v0);
+    if (compact_fits_lds(v.N, lds_bytes)) compact_lds<B>(v, s_scan, lds_bytes);
+    else compact_mem<B>(v, s_scan);
 }
 
 }  // namespace sbt
