@@ -321,7 +321,7 @@ def serving_leg(params, seconds, fraction=0.5):
     from paper_2207_03936_amd import serve_bench, synth
     pool = synth.make_batch("serve", 2000)
     srv = serve_bench.make_server(params)
-    sat = serve_bench.run_rate(srv, pool, 0, 0, max_events=40_000)
+    sat = serve_bench.saturation(srv, pool, 40_000)
     rate = fraction * sat["sustained_events_per_s"]
     res = serve_bench.run_rate(srv, pool, rate, seconds)
     srv.close()
