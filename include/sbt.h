@@ -336,6 +336,11 @@ typedef struct sbt_server_config {
     int32_t slot_events;         /* events per batch (>= 1)                        */
     int32_t slot_hits;           /* hits per batch (>= 65,535 so any event fits)   */
     int32_t max_wait_us;         /* launch a partial batch after this wait         */
+    int32_t coords_f16;          /* 1: hits travel to the device as binary16 (each
+                                    coordinate rounded to nearest even on the host,
+                                    8 bytes per hit instead of 12); results are those
+                                    of the rounded hits, as sbt_reconstruct_batched_f16
+                                    gives them.  0: binary32.                       */
 } sbt_server_config;
 
 /* A completed event: its tracks in the same CSR form as one event of

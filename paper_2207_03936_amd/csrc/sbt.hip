@@ -1093,10 +1093,11 @@ int launch_batched_raw(const sbt_params &params, const sbt_tuning &tuning, const
     return launch_batched(params, tuning, H, W, O, stream, nullptr);
 }
 
-int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
-                          const EventOut &out, void *workspace, hipStream_t stream)
+namespace {
+
+int batched_events(const sbt_params &params, const sbt_tuning &tuning, const HitsArgs &H, const EventOut &out,
+                   void *workspace, hipStream_t stream)
 {
-    const HitsArgs H = hits_args(&hits);
     if (H.n_events == 0) return SBT_ERR_INVALID_ARG;
     Work W;
     carve(H.n_events, H.n_hits, (char *)workspace, &W);
@@ -1110,6 +1111,20 @@ int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, co
     hipLaunchKernelGGL(k_write_events, dim3(std::min(H.n_events, 8192)), dim3(kWriteThreads), 0, stream, H, W,
                        out);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+}
+
+}  // namespace
+
+int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
+                          const EventOut &out, void *workspace, hipStream_t stream)
+{
+    return batched_events(params, tuning, hits_args(&hits), out, workspace, stream);
+}
+
+int launch_batched_events_f16(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits_f16 &hits,
+                              const EventOut &out, void *workspace, hipStream_t stream)
+{
+    return batched_events(params, tuning, hits_args_f16(&hits), out, workspace, stream);
 }
 
 sbt_tuning default_tuning_config() { return default_tuning(); }

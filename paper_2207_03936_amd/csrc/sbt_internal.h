@@ -28,9 +28,12 @@ struct EventOut {
     int32_t *th;      // [sum of track lengths] hit ids, event by event
 };
 
-// The batched sequence writing per-event lists (E >= 1).
+// The batched sequence writing per-event lists (E >= 1), from binary32 or
+// binary16 hits.
 int launch_batched_events(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits &hits,
                           const EventOut &out, void *workspace, hipStream_t stream);
+int launch_batched_events_f16(const sbt_params &params, const sbt_tuning &tuning, const sbt_hits_f16 &hits,
+                              const EventOut &out, void *workspace, hipStream_t stream);
 
 // The library's default launch configuration, and the one it chooses for a
 // batch of E events and H hits on a device of `cus` compute units.

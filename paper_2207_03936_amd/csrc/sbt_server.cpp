@@ -19,8 +19,10 @@
 // kernels, so a slot's H2D copy never queues behind another slot's output
 // copy waiting for its kernels, and the host does not copy results.  The hits
 // of a slot's events are copied into its pinned staging at launch by a small
-// pool of threads owned by the server, in parallel over events.
+// pool of threads owned by the server, in parallel over events; with
+// binary16 transfer the same threads round them to 8-byte records on the way.
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
 
 #include <stdint.h>
 #include <string.h>
@@ -213,7 +215,7 @@ SlotLayout slot_layout(const sbt_server_config &c, int M)
     size_t o = 0;
     L.eo = o; o += align_up(4 * (E + 1));
     L.mo = o; o += align_up(4 * (E * M + 1));
-    L.xyz = o; o += 3 * align_up(4 * H);
+    L.xyz = o; o += c.coords_f16 ? align_up(8 * H) : 3 * align_up(4 * H);
     L.in_total = o;
     L.work = align_up(sbt::workspace_bytes(c.slot_events, c.slot_hits));
     L.device_total = L.in_total + L.work;
@@ -229,6 +231,53 @@ SlotLayout slot_layout(const sbt_server_config &c, int M)
 
 // bytes from one of x, y, z to the next for a launch of H hits
 size_t xyz_stride(size_t H) { return align_up(4 * H); }
+
+// Binary16 records of n hits, each x | y << 16 and z (upper half zero) in two
+// 32-bit words, the layout of sbt_hits_f16; every coordinate is rounded to
+// the nearest binary16, ties to even.  Eight hits per step with the F16C
+// conversion, the rest one by one.
+__attribute__((target("avx,f16c"))) void half_records_f16c(const float *x, const float *y, const float *z, int n,
+                                                           uint16_t *out)
+{
+    const __m128i zero = _mm_setzero_si128();
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        const __m128i hx = _mm256_cvtps_ph(_mm256_loadu_ps(x + i), _MM_FROUND_TO_NEAREST_INT);
+        const __m128i hy = _mm256_cvtps_ph(_mm256_loadu_ps(y + i), _MM_FROUND_TO_NEAREST_INT);
+        const __m128i hz = _mm256_cvtps_ph(_mm256_loadu_ps(z + i), _MM_FROUND_TO_NEAREST_INT);
+        const __m128i xy_lo = _mm_unpacklo_epi16(hx, hy), xy_hi = _mm_unpackhi_epi16(hx, hy);
+        const __m128i z_lo = _mm_unpacklo_epi16(hz, zero), z_hi = _mm_unpackhi_epi16(hz, zero);
+        __m128i *o = reinterpret_cast<__m128i *>(out + 4 * (size_t)i);
+        _mm_storeu_si128(o + 0, _mm_unpacklo_epi32(xy_lo, z_lo));
+        _mm_storeu_si128(o + 1, _mm_unpackhi_epi32(xy_lo, z_lo));
+        _mm_storeu_si128(o + 2, _mm_unpacklo_epi32(xy_hi, z_hi));
+        _mm_storeu_si128(o + 3, _mm_unpackhi_epi32(xy_hi, z_hi));
+    }
+    for (; i < n; ++i) {
+        out[4 * (size_t)i + 0] = _cvtss_sh(x[i], _MM_FROUND_TO_NEAREST_INT);
+        out[4 * (size_t)i + 1] = _cvtss_sh(y[i], _MM_FROUND_TO_NEAREST_INT);
+        out[4 * (size_t)i + 2] = _cvtss_sh(z[i], _MM_FROUND_TO_NEAREST_INT);
+        out[4 * (size_t)i + 3] = 0;
+    }
+}
+
+// the same without F16C
+void half_records_portable(const float *x, const float *y, const float *z, int n, uint16_t *out)
+{
+    for (int i = 0; i < n; ++i) {
+        out[4 * (size_t)i + 0] = __builtin_bit_cast(uint16_t, (_Float16)x[i]);
+        out[4 * (size_t)i + 1] = __builtin_bit_cast(uint16_t, (_Float16)y[i]);
+        out[4 * (size_t)i + 2] = __builtin_bit_cast(uint16_t, (_Float16)z[i]);
+        out[4 * (size_t)i + 3] = 0;
+    }
+}
+
+void half_records(const float *x, const float *y, const float *z, int n, uint16_t *out)
+{
+    static const bool f16c = __builtin_cpu_supports("f16c") && __builtin_cpu_supports("avx");
+    if (f16c) half_records_f16c(x, y, z, n, out);
+    else half_records_portable(x, y, z, n, out);
+}
 
 void free_slot(Slot &s)
 {
@@ -324,36 +373,55 @@ int launch(sbt_server *srv, Slot &s)
     hipStream_t st = s.stream;
     std::shared_ptr<ResultBlock> block = free_block(srv, L);
     if (!block) return SBT_ERR_NOMEM;
-    // hits into the pinned staging, x, y, z packed for this launch, in parallel over events
+    // hits into the pinned staging, packed for this launch, in parallel over
+    // events: x, y, z arrays, or binary16 records
+    const bool f16 = srv->cfg.coords_f16 != 0;
     float *hx = (float *)(s.hin + L.xyz), *hy = (float *)(s.hin + L.xyz + stride),
           *hz = (float *)(s.hin + L.xyz + 2 * stride);
+    uint16_t *h16 = (uint16_t *)(s.hin + L.xyz);
     srv->pool->run((int)s.events.size(), [&](int i) {
         SlotEvent &ev = s.events[(size_t)i];
         if (ev.n > 0) {
-            memcpy(hx + ev.base, ev.x, sizeof(float) * ev.n);
-            memcpy(hy + ev.base, ev.y, sizeof(float) * ev.n);
-            memcpy(hz + ev.base, ev.z, sizeof(float) * ev.n);
+            if (f16) {
+                half_records(ev.x, ev.y, ev.z, ev.n, h16 + 4 * (size_t)ev.base);
+            } else {
+                memcpy(hx + ev.base, ev.x, sizeof(float) * ev.n);
+                memcpy(hy + ev.base, ev.y, sizeof(float) * ev.n);
+                memcpy(hz + ev.base, ev.z, sizeof(float) * ev.n);
+            }
         }
         std::vector<float>().swap(ev.own);
     });
     // offsets and hits in one copy
-    if (hipMemcpyAsync(s.dmem, s.hin, L.xyz + 3 * stride, hipMemcpyHostToDevice, st) != hipSuccess)
-        return SBT_ERR_HIP;
-    sbt_hits hits;
-    hits.n_events = (int32_t)E;
-    hits.n_hits = (int32_t)H;
-    hits.event_offsets = (const int32_t *)(s.dmem + L.eo);
-    hits.module_offsets = (const int32_t *)(s.dmem + L.mo);
-    hits.x = (const float *)(s.dmem + L.xyz);
-    hits.y = (const float *)(s.dmem + L.xyz + stride);
-    hits.z = (const float *)(s.dmem + L.xyz + 2 * stride);
+    const size_t in_bytes = L.xyz + (f16 ? 8 * H : 3 * stride);
+    if (hipMemcpyAsync(s.dmem, s.hin, in_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return SBT_ERR_HIP;
     sbt::EventOut out;
     out.eto = block->eto;
     out.status = block->st;
     out.hoff = block->hoff;
     out.tho = block->tho;
     out.th = block->th;
-    int rc = sbt::launch_batched_events(srv->params, launch_tuning(srv, (int)E, (int)H), hits, out, s.dwork, st);
+    const sbt_tuning tuning = launch_tuning(srv, (int)E, (int)H);
+    int rc;
+    if (f16) {
+        sbt_hits_f16 hits;
+        hits.n_events = (int32_t)E;
+        hits.n_hits = (int32_t)H;
+        hits.event_offsets = (const int32_t *)(s.dmem + L.eo);
+        hits.module_offsets = (const int32_t *)(s.dmem + L.mo);
+        hits.xyzw = (const uint16_t *)(s.dmem + L.xyz);
+        rc = sbt::launch_batched_events_f16(srv->params, tuning, hits, out, s.dwork, st);
+    } else {
+        sbt_hits hits;
+        hits.n_events = (int32_t)E;
+        hits.n_hits = (int32_t)H;
+        hits.event_offsets = (const int32_t *)(s.dmem + L.eo);
+        hits.module_offsets = (const int32_t *)(s.dmem + L.mo);
+        hits.x = (const float *)(s.dmem + L.xyz);
+        hits.y = (const float *)(s.dmem + L.xyz + stride);
+        hits.z = (const float *)(s.dmem + L.xyz + 2 * stride);
+        rc = sbt::launch_batched_events(srv->params, tuning, hits, out, s.dwork, st);
+    }
     if (rc) return rc;
     if (hipEventRecord(s.done, st) != hipSuccess) return SBT_ERR_HIP;
     s.block = std::move(block);
@@ -450,7 +518,8 @@ int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const 
     if (rc) return rc;
     if (!config || !out) return SBT_ERR_INVALID_ARG;
     const sbt_server_config &c = *config;
-    if (c.n_slots < 1 || c.slot_events < 1 || c.slot_hits < SBT_MAX_EVENT_HITS || c.max_wait_us < 0)
+    if (c.n_slots < 1 || c.slot_events < 1 || c.slot_hits < SBT_MAX_EVENT_HITS || c.max_wait_us < 0 ||
+        (c.coords_f16 != 0 && c.coords_f16 != 1))
         return SBT_ERR_INVALID_ARG;
     sbt_tuning t = tuning ? *tuning : sbt::default_tuning_config();
     if ((rc = sbt::tuning_valid(t))) return rc;

@@ -95,7 +95,7 @@ class SbtTuning(ctypes.Structure):
 class SbtServerConfig(ctypes.Structure):
     _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int32),
                 ("slot_events", ctypes.c_int32), ("slot_hits", ctypes.c_int32),
-                ("max_wait_us", ctypes.c_int32)]
+                ("max_wait_us", ctypes.c_int32), ("coords_f16", ctypes.c_int32)]
 
 
 class SbtServerResult(ctypes.Structure):
@@ -542,11 +542,14 @@ class Server:
     """sbt_server: continuous batching over resident device slots."""
 
     def __init__(self, params: SbtParams, device_budget_bytes: int, n_slots: int = 4, slot_events: int = 256,
-                 slot_hits: int = 1 << 21, max_wait_us: int = 200, tuning: Optional[SbtTuning] = None):
+                 slot_hits: int = 1 << 21, max_wait_us: int = 200, tuning: Optional[SbtTuning] = None,
+                 coords_f16: bool = False):
+        """coords_f16: hits travel to the device as binary16 (rounded on the
+        host); results are those of the rounded hits."""
         _torch()
         self.n_modules = params.n_modules
         cfg = SbtServerConfig(int(device_budget_bytes), int(n_slots), int(slot_events), int(slot_hits),
-                              int(max_wait_us))
+                              int(max_wait_us), 1 if coords_f16 is True else int(coords_f16))
         h = ctypes.c_void_p(0)
         _check(lib().sbt_server_create(ctypes.byref(params), ctypes.byref(tuning) if tuning else None,
                                        ctypes.byref(cfg), ctypes.byref(h)), "sbt_server_create")

@@ -27,9 +27,9 @@ from . import sbt, synth
 
 
 def make_server(params, budget_bytes=8 << 30, n_slots=4, slot_events=512, slot_hits=3 << 20, max_wait_us=300,
-                tuning=None):
+                tuning=None, coords_f16=False):
     return sbt.Server(params, device_budget_bytes=budget_bytes, n_slots=n_slots, slot_events=slot_events,
-                      slot_hits=slot_hits, max_wait_us=max_wait_us, tuning=tuning)
+                      slot_hits=slot_hits, max_wait_us=max_wait_us, tuning=tuning, coords_f16=coords_f16)
 
 
 def run_rate(srv, pool, rate, seconds, seed=123, max_events=2_000_000):
@@ -71,13 +71,14 @@ def main(argv=None):
     ap.add_argument("--slot-hits", type=int, default=3 << 20)
     ap.add_argument("--max-wait-us", type=int, default=300)
     ap.add_argument("--max-events", type=int, default=40_000_000, help="cap on arrivals per rate")
+    ap.add_argument("--f16", action="store_true", help="hits travel to the device as binary16")
     args = ap.parse_args(argv)
     import torch
     assert torch.cuda.is_available(), "serving needs a GPU"
     pool = synth.make_batch("serve", args.pool)
     params = sbt.make_params(pool.module_z)
     srv = make_server(params, int(args.budget_gib * (1 << 30)), args.slots, args.slot_events, args.slot_hits,
-                      args.max_wait_us)
+                      args.max_wait_us, coords_f16=args.f16)
     sat = saturation(srv, pool, args.saturation_events)
     cap = sat["sustained_events_per_s"]
     print(json.dumps(dict(kind="saturation", config=vars(args), **sat)), flush=True)

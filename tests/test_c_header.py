@@ -56,3 +56,46 @@ def test_c_program_links_and_runs(tmp_path):
     assert out.returncode == 0, out.stdout + out.stderr
     msg, cut, nbytes = out.stdout.strip().split("|")
     assert msg == "workspace or context too small" and cut == "40" and int(nbytes) > 0
+
+
+LAYOUT = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "sbt.h"
+
+#define FIELD(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void)
+{
+    printf("sbt_params %zu\nsbt_tuning %zu\nsbt_hits %zu\nsbt_hits_f16 %zu\nsbt_tracks %zu\n",
+           sizeof(sbt_params), sizeof(sbt_tuning), sizeof(sbt_hits), sizeof(sbt_hits_f16), sizeof(sbt_tracks));
+    printf("sbt_server_config %zu\nsbt_server_result %zu\n", sizeof(sbt_server_config), sizeof(sbt_server_result));
+    FIELD(sbt_server_config, coords_f16);
+    FIELD(sbt_server_result, t_done_us);
+    FIELD(sbt_params, max_event_hits);
+    return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """The ctypes structures of the Python binding have the sizes and field
+    offsets that a C compiler gives the header's structures."""
+    import ctypes
+    from paper_2207_03936_amd import sbt
+    src = tmp_path / "layout.c"
+    src.write_text(LAYOUT)
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    want = {
+        "sbt_params": ctypes.sizeof(sbt.SbtParams), "sbt_tuning": ctypes.sizeof(sbt.SbtTuning),
+        "sbt_hits": ctypes.sizeof(sbt.SbtHits), "sbt_hits_f16": ctypes.sizeof(sbt.SbtHitsF16),
+        "sbt_tracks": ctypes.sizeof(sbt.SbtTracks), "sbt_server_config": ctypes.sizeof(sbt.SbtServerConfig),
+        "sbt_server_result": ctypes.sizeof(sbt.SbtServerResult),
+        "sbt_server_config.coords_f16": sbt.SbtServerConfig.coords_f16.offset,
+        "sbt_server_result.t_done_us": sbt.SbtServerResult.t_done_us.offset,
+        "sbt_params.max_event_hits": sbt.SbtParams.max_event_hits.offset,
+    }
+    assert {k: int(v) for k, v in got.items()} == want

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
+from _util import rounded_to_f16
 from paper_2207_03936_amd import sbt, synth
 
 pytestmark = pytest.mark.gpu
@@ -58,15 +59,17 @@ def _drain(srv, want_n, timeout_s=60.0):
     return got
 
 
-def test_served_results_equal_alone():
+@pytest.mark.parametrize("coords_f16", [False, True])
+def test_served_results_equal_alone(coords_f16):
     """Bursts of events arrive while earlier ones are on the GPU; small slots
-    force many launches on several streams at once."""
-    say("serving mix vs alone")
+    force many launches on several streams at once.  With binary16 transfer
+    the results are the oracle's on the rounded coordinates."""
+    say(f"serving mix vs alone, binary16 transfer {coords_f16}")
     b = synth.make_batch("mu1-25", 120)
-    want = _oracle_tracks(b)
+    want = _oracle_tracks(rounded_to_f16(b) if coords_f16 else b)
     params = sbt.make_params(b.module_z)
     srv = sbt.Server(params, device_budget_bytes=2 << 30, n_slots=3, slot_events=16, slot_hits=1 << 17,
-                     max_wait_us=50)
+                     max_wait_us=50, coords_f16=coords_f16)
     got = {}
     rng = np.random.default_rng(9)
     e = 0
@@ -115,6 +118,10 @@ def test_admission_rules():
     with pytest.raises(sbt.SbtError) as ei:
         sbt.Server(params, device_budget_bytes=1 << 20, n_slots=2, slot_events=8, slot_hits=1 << 16)
     assert ei.value.code == sbt.SBT_ERR_WORKSPACE
+    # the transfer format is 0 or 1
+    with pytest.raises(sbt.SbtError) as ei:
+        sbt.Server(params, device_budget_bytes=1 << 30, n_slots=1, slot_events=2, slot_hits=1 << 16, coords_f16=2)
+    assert ei.value.code == sbt.SBT_ERR_INVALID_ARG
     srv = sbt.Server(params, device_budget_bytes=1 << 30, n_slots=1, slot_events=2, slot_hits=1 << 16,
                      max_wait_us=1000)
     # oversized and malformed events are refused at submission
