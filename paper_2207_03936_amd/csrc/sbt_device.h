@@ -1336,6 +1336,17 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
     __syncthreads();
     uint16_t *l0 = kLds ? Lay<CAP>::al(0) : v.list(kListAct0);
     uint16_t *l1 = kLds ? Lay<CAP>::al(1) : v.list(kListAct1);
+    // the last traversal index whose seeding can make a seed: its modules
+    // t-2, t-1 and t all hold hits (2 when no index can)
+    int last_seed = 2;
+    for (int u = M - 1; u > 2; --u) {
+        const int k0 = kmod(P, u), k1 = kmod(P, u - 1), k2 = kmod(P, u - 2);
+        if (S.mo[k0 + 1] > S.mo[k0] && S.mo[k1 + 1] > S.mo[k1] && S.mo[k2 + 1] > S.mo[k2]) {
+            last_seed = u;
+            break;
+        }
+    }
+    last_seed = uni(last_seed);
     int par = 0;
     stage_seed_follow<B, kLds, CAP>(PP, v, 2, S, own, l0, &S.cnt[1], 0, M > 3);
     __syncthreads();
@@ -1345,6 +1356,9 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
         // t done: resolve t keeping the survivors in nxt, then seed t and
         // search t+1
         const int n_act = uni(S.cnt[1 + par]);
+        // with no forming track and no seed possible from here on, the
+        // remaining steps change nothing
+        if (n_act == 0 && t > last_seed) break;
         uint16_t *act = par ? l1 : l0;
         uint16_t *nxt = par ? l0 : l1;
         const bool more = t + 1 < M;
