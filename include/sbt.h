@@ -286,6 +286,12 @@ int sbt_debug_phi_sort_rank(const sbt_params *params, const sbt_hits *hits, uint
                             uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* The host conversion of the server's binary16 transfer: n hits from binary32
+ * x, y, z (HOST memory) to the 8-byte records of sbt_hits_f16 (x, y, z, 0;
+ * each rounded to the nearest binary16, ties to even) in `out` (HOST, 4n
+ * uint16).  SBT_OK, or SBT_ERR_INVALID_ARG for null pointers or n < 0.     */
+int sbt_debug_half_records(const float *x, const float *y, const float *z, int32_t n, uint16_t *out);
+
 /* ---- the steps around Search by triplet in the paper's sequence (Section 4) ----------
  *
  * Global event cut: the threshold on the hit count that rejects at most

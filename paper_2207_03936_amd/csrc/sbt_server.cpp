@@ -509,6 +509,13 @@ int step(sbt_server *srv)
 
 extern "C" {
 
+int sbt_debug_half_records(const float *x, const float *y, const float *z, int32_t n, uint16_t *out)
+{
+    if (!x || !y || !z || !out || n < 0) return SBT_ERR_INVALID_ARG;
+    half_records(x, y, z, n, out);
+    return SBT_OK;
+}
+
 double sbt_now_us(void) { return now_us(); }
 
 int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const sbt_server_config *config,

@@ -127,6 +127,7 @@ PROTOTYPES = {
     "sbt_context_stage_ms": (ctypes.c_int, [_VP, _P(ctypes.c_float), ctypes.c_int32]),
     "sbt_debug_phi_sort": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "sbt_debug_phi_sort_rank": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
+    "sbt_debug_half_records": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP]),
     "sbt_server_create": (ctypes.c_int, [_P(SbtParams), _P(SbtTuning), _P(SbtServerConfig), _P(_VP)]),
     "sbt_server_destroy": (None, [_VP]),
     "sbt_server_submit": (ctypes.c_int, [_VP, ctypes.c_int64, ctypes.c_int32, _P(ctypes.c_int32),
@@ -242,6 +243,20 @@ def to_f16_aos(x, y, z) -> np.ndarray:
     out[:, 1] = np.asarray(y, np.float32)
     out[:, 2] = np.asarray(z, np.float32)
     return out.view(np.uint16)
+
+
+def half_records(x, y, z) -> np.ndarray:
+    """The server's host conversion for binary16 transfer (sbt_debug_half_records):
+    [n, 4] uint16 records x, y, z, 0, each rounded to the nearest binary16."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    z = np.ascontiguousarray(z, np.float32)
+    n = int(x.shape[0])
+    assert y.shape == (n,) and z.shape == (n,)
+    out = np.full((n, 4), 0xFFFF, np.uint16)
+    _check(lib().sbt_debug_half_records(x.ctypes.data, y.ctypes.data, z.ctypes.data, n, out.ctypes.data),
+           "sbt_debug_half_records")
+    return out
 
 
 class DeviceBatchF16:

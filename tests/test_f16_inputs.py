@@ -58,3 +58,25 @@ def test_physics_holds_on_half_precision_coordinates():
     assert res["efficiency"] >= 0.98
     assert res["fake_fraction"] <= 0.01
     assert res["hit_purity"] >= 0.99
+
+
+def test_server_conversion_matches_numpy():
+    """The server's host conversion (F16C where the CPU has it, eight hits at
+    a time, then one by one) gives numpy's binary16 rounding bit for bit:
+    ties to even, subnormals, signed zeros, values near the binary16 limit,
+    and lengths that are not a multiple of eight."""
+    import os
+    if not os.path.exists(sbt.LIB_PATH):
+        import pytest
+        pytest.skip("libsbt.so is not built")
+    rng = np.random.default_rng(16)
+    one = np.float32(1.0)
+    ulp = np.float32(2.0 ** -10)
+    special = np.array([0.0, -0.0, one + ulp / 2, one + 3 * ulp / 2, -(one + ulp / 2), 6.0e-8, -3.0e-6, 2.0 ** -24,
+                        65504.0, -65504.0, 65519.0, 725.0, -275.0, 41.99, 1e-3, 123.456], np.float32)
+    for n in (0, 1, 7, 8, 9, 16, 23, 1000, 4097):
+        x = np.concatenate([special, rng.normal(0, 40, n).astype(np.float32)])[:n]
+        y = rng.uniform(-60, 60, n).astype(np.float32)
+        z = rng.choice(np.float32(synth.PLANE_Z), n).astype(np.float32) + rng.normal(0, 2, n).astype(np.float32)
+        got = sbt.half_records(x, y, z)
+        assert np.array_equal(got, sbt.to_f16_aos(x, y, z)), n
