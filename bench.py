@@ -10,7 +10,8 @@ over slices of the batch.  Further legs, each reported apart from `value`:
 the insertion-rank sort beside the bucket sort; binary16 input; end to end
 from pinned host memory (one stream, then three); the paper's sequence
 around the method (event cut, transfer, reconstruction, consolidation); a
-short serving leg with p50/p99 event latency under continuous batching; and
+short serving leg with p50/p99 event latency under continuous batching (and
+the same with hits sent to the device as binary16, at 80 % of its burst rate); and
 the CPU oracle on a bounded sample of the same events, on one core and on
 all of them.
 
@@ -314,13 +315,13 @@ def cpu_parallel_baseline(batch, workload, procs, target_s=6.0):
 _PAR_BATCH = None
 
 
-def serving_leg(params, seconds, fraction=0.5):
+def serving_leg(params, seconds, fraction=0.5, coords_f16=False):
     """Continuous-batching server fed by Poisson arrivals of events from the
     mu ~ U{1..25} serving mixture: saturated throughput first, then latency
-    percentiles at `fraction` of it."""
+    percentiles at `fraction` of it.  coords_f16: hits sent as binary16."""
     from paper_2207_03936_amd import serve_bench, synth
     pool = synth.make_batch("serve", 2000)
-    srv = serve_bench.make_server(params)
+    srv = serve_bench.make_server(params, coords_f16=coords_f16)
     sat = serve_bench.saturation(srv, pool, 40_000)
     rate = fraction * sat["sustained_events_per_s"]
     res = serve_bench.run_rate(srv, pool, rate, seconds)
@@ -532,6 +533,9 @@ def main():
     if not args.no_serve:
         result["serving"] = serving_leg(params, args.serve_seconds)
         result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
+        # the same with hits sent to the device as binary16 (results are those
+        # of the rounded hits): 80 % of its own burst saturation
+        result["serving_f16"] = serving_leg(params, args.serve_seconds, fraction=0.8, coords_f16=True)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(batch, got, args.workload)
         result["cpu_baseline_all_cores"] = cpu_par
