@@ -231,7 +231,9 @@ typedef struct sbt_context sbt_context;
  * most one event per compute unit, or at most two of 4,000 hits or more on
  * average; otherwise 512 lanes, two workgroups per compute unit, and 768-hit
  * slots for events of 4,000 hits or more on average, 672-hit slots for
- * smaller ones (lds_owner_hits 16,384 throughout).  sbt_context_set_tuning
+ * smaller ones, except that more than twelve smaller events per compute unit
+ * run 256 lanes, three workgroups per compute unit, 448-hit slots
+ * (lds_owner_hits 16,384 throughout).  sbt_context_set_tuning
  * and sbt_autotune install one configuration for every later call;
  * sbt_context_get_tuning reports the installed one, or without one the
  * choice for a batch of max_events events and max_hits hits.  Results never

@@ -821,7 +821,10 @@ sbt_tuning default_tuning()
 // sooner, and there are too few events to fill the device twice.  Larger
 // batches run 512 lanes, two workgroups per CU; batches of large events take
 // 768-hit slots (the largest that still fit two workgroups' LDS on a CU), so
-// that their busiest modules stay in LDS rather than in memory.
+// that their busiest modules stay in LDS rather than in memory.  Batches of
+// more than twelve smaller events per CU are throughput-bound rather than
+// bound by their largest event, and run 256 lanes, three workgroups per CU,
+// with 448-hit slots: more events in flight on the lanes they use.
 sbt_tuning size_tuning(int E, int H, int cus)
 {
     sbt_tuning t = default_tuning();
@@ -832,6 +835,10 @@ sbt_tuning size_tuning(int E, int H, int cus)
         t.lds_window_hits = 1536;
     } else if (large) {
         t.lds_window_hits = 768;
+    } else if (E > 12 * cus) {
+        t.threads_per_event = 256;
+        t.blocks_per_cu = 3;
+        t.lds_window_hits = 448;
     }
     return t;
 }

@@ -395,10 +395,13 @@ def _expected_choice(n_events, n_hits, cus):
     large = n_hits >= 4000 * n_events
     if n_events <= cus or (n_events <= 2 * cus and large):
         return (1024, 1, 1536)
+    if not large and n_events > 12 * cus:
+        return (256, 3, 448)
     return (512, 2, 768 if large else 672)
 
 
-@pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000)])
+@pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000),
+                                      ("mu7.6", 3600)])
 def test_configuration_chosen_per_call(config, n):
     """A context created without a launch configuration chooses one per call
     from the batch's size.  Each choice, a smaller batch through the same
