@@ -4,16 +4,22 @@ Workload: the fixed batch of 1,000 upgrade-like events (Poisson(7.6)
 vertices, Poisson(40) tracks each, 26 planes), synthetic and seeded.  A step
 is one pass of the whole hot path (phi sort, seeding and following, tracklet
 filter, compaction) over the batch, with inputs and outputs resident in HBM.
-`value` is the batched path (persistent kernel + captured graph); the plain
-per-event kernels are timed beside it, on one stream and on 2 and 3 streams
-over slices of the batch.  Further legs, each reported apart from `value`:
-the insertion-rank sort beside the bucket sort; binary16 input; end to end
-from pinned host memory (one stream, then three); the paper's sequence
-around the method (event cut, transfer, reconstruction, consolidation); a
-short serving leg with p50/p99 event latency under continuous batching (and
-the same with hits sent to the device as binary16, at 80 % of its burst rate); and
-the CPU oracle on a bounded sample of the same events, on one core and on
-all of them.
+`value` is the batched path: the persistent kernel and its tail captured as
+one HIP graph and replayed on a stream of its own, in the launch
+configuration the library chooses for the batch's size.  Beside it: the same
+sequence launched directly (`direct_ms`), per-run HIP-event times (median and
+min), the plain per-event kernels on one stream and on 2 and 3 streams over
+slices of the batch, and the autotuner's pick.  Further legs, each reported
+apart from `value`: the insertion-rank sort beside the bucket sort; the
+paper's separate candidate pass before seeding beside the fused search; binary16
+input; end to end from pinned host memory (one stream, then three); the
+paper's sequence around the method (event cut, transfer, reconstruction,
+consolidation); the uneven mu ~ U{1..25} x 10,000 and the dense mu = 30 x
+2,000 batches (autotuned, each against the oracle on a sample); a short
+serving leg with p50/p99 event latency under continuous batching (and the
+same with hits sent to the device as binary16, at 80 % of its burst rate);
+and the CPU oracle on a bounded sample of the same events, on one core and
+on the host's CPU share.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -26,6 +32,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -42,6 +49,11 @@ WORKLOADS = {
             "20% of tracks kinked by N(0, 2 mrad) (seed 4)",
 }
 KERNEL = "k_persistent"
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(batch, eto, tho) -> int:
@@ -64,30 +76,55 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(per_launch_hits: int):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_persistent_mu7.6_x1000_traffic.json")
+def _summary(name, per_launch_hits: int, tuning: dict):
+    """A committed counter summary of the dominant kernel, if it was taken on
+    the current kernel source, the same batch and the same launch
+    configuration (lanes per event, workgroups per CU, LDS slot capacity);
+    else None."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n_hits") != per_launch_hits:
         return None
-    return d.get("hbm_bytes_per_launch")
-
-
-def measured_sq(per_launch_hits: int):
-    """Instruction counts of the dominant kernel from the committed SQ counter
-    summary, if taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_persistent_mu7.6_x1000_sq.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        d = json.load(f)
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n_hits") != per_launch_hits:
+    want = {k: int(tuning[k]) for k in TUNING_KEYS}
+    if {k: d.get("tuning", {}).get(k) for k in TUNING_KEYS} != want:
         return None
     return d
+
+
+TUNING_KEYS = ("threads_per_event", "blocks_per_cu", "lds_window_hits")
+
+
+def measured_traffic(per_launch_hits: int, tuning: dict):
+    """Bytes per launch of the dominant kernel between L2 and the memory
+    fabric (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a copy
+    of known size) from the committed summary, or None."""
+    d = _summary("k_persistent_mu7.6_x1000_traffic.json", per_launch_hits, tuning)
+    return None if d is None else d.get("fabric_bytes_per_launch")
+
+
+def measured_sq(per_launch_hits: int, tuning: dict):
+    """Instruction counts of the dominant kernel from the committed SQ counter
+    summary, or None."""
+    return _summary("k_persistent_mu7.6_x1000_sq.json", per_launch_hits, tuning)
+
+
+def host_cpu():
+    """CPU model and logical CPU count of this host (lscpu)."""
+    model, cpus = None, os.cpu_count()
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+            elif k.strip() == "CPU(s)":
+                cpus = int(v.strip())
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return dict(cpu_model=model, host_cpus=cpus)
 
 
 def copy_bandwidth(torch, mib=1024, reps=10):
@@ -315,10 +352,12 @@ def cpu_parallel_baseline(batch, workload, procs, target_s=6.0):
 _PAR_BATCH = None
 
 
-def serving_leg(params, seconds, fraction=0.5, coords_f16=False):
+def serving_leg(params, seconds, fraction=0.5, coords_f16=False, bytes_per_event=None):
     """Continuous-batching server fed by Poisson arrivals of events from the
     mu ~ U{1..25} serving mixture: saturated throughput first, then latency
-    percentiles at `fraction` of it.  coords_f16: hits sent as binary16."""
+    percentiles at `fraction` of it.  coords_f16: hits sent as binary16.
+    bytes_per_event: the pool's algorithmic bytes per event, to state the
+    sustained rate as a fraction of the HBM bandwidth."""
     from paper_2207_03936_amd import serve_bench, synth
     pool = synth.make_batch("serve", 2000)
     srv = serve_bench.make_server(params, coords_f16=coords_f16)
@@ -328,6 +367,10 @@ def serving_leg(params, seconds, fraction=0.5, coords_f16=False):
     srv.close()
     res["saturation_events_per_s"] = sat["sustained_events_per_s"]
     res["workload"] = "Poisson arrivals of mu ~ U{1..25} events (pool of 2,000, seed 5)"
+    if bytes_per_event:
+        gbps = res["sustained_events_per_s"] * bytes_per_event / 1e9
+        res["hbm"] = {"algorithmic_bytes_per_event": round(bytes_per_event, 1), "achieved_GBps": round(gbps, 3),
+                      "peak_GBps": HBM_PEAK_GBPS, "frac": round(gbps / HBM_PEAK_GBPS, 6)}
     return res
 
 
@@ -353,13 +396,107 @@ def cpu_baseline(batch, gpu_out, workload="mu7.6", target_s=10.0):
         done = time.perf_counter() - t
         if done >= 0.9 * target_s:
             break
-    eto, tho, th = gpu_out[:3]
-    T = int(eto[n])
-    ok = (np.array_equal(eto[:n + 1], want[0]) and np.array_equal(tho[:T + 1], want[1])
-          and np.array_equal(th[:int(tho[T])], want[2]))
+    ok = sample_matches(gpu_out, want, n)
     return dict(value=round(passes * n / done, 2), unit="events/s", cores=1, kind="oracle",
                 sample=f"first {n} events of the {workload} batch, {passes} pass(es), single thread",
                 hits_per_s=round(passes * int(sub.n_hits) / done, 1), gpu_matches_oracle_on_sample=bool(ok))
+
+
+def sample_matches(gpu_out, want, n):
+    """Whether the first n events of a GPU output equal the oracle's tracks
+    for those events (CSR arrays byte for byte)."""
+    eto, tho, th = gpu_out[:3]
+    T = int(eto[n])
+    return bool(np.array_equal(eto[:n + 1], want[0]) and np.array_equal(tho[:T + 1], want[1])
+                and np.array_equal(th[:int(tho[T])], want[2]))
+
+
+def event_times(torch, fn, stream, runs=20, warmup=3):
+    """Milliseconds of each of `runs` back-to-back calls, from HIP events
+    recorded on `stream` around each call: (median, min)."""
+    for _ in range(warmup):
+        fn()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    for a, b in pairs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    stream.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in pairs)
+    return float(np.median(ms)), float(ms[0])
+
+
+def kernel_ms(ctx, dev, out, stream, n):
+    """Mean milliseconds of the persistent kernel, the scan and the CSR write
+    over n direct launches, from the context's HIP events on `stream`."""
+    ctx.set_profiling(True)
+    stage = np.zeros(3)
+    for _ in range(n):
+        ctx.reconstruct(dev, out, stream)
+        stage += np.array(ctx.stage_ms())
+    ctx.set_profiling(False)
+    return stage / n
+
+
+def workload_leg(torch, sbt, batch, workload, steps, warmup, stream, oracle_events):
+    """One more batch on the batched path in the autotuner's configuration:
+    events/s and hits/s of graph replays (wall clock over `steps`, and the
+    median and min of 20 HIP-event-timed runs), the persistent kernel's
+    algorithmic HBM rate, the plain per-event kernels, and the GPU's tracks
+    against the oracle on the batch's first events."""
+    import oracle
+    E, H = batch.n_events, batch.n_hits
+    params = sbt.make_params(batch.module_z)
+    dev = sbt.DeviceBatch(batch)
+    out = sbt.DeviceTracks(E, H)
+    ctx = sbt.Context(params, E, H)
+    rule = ctx.get_tuning().as_dict()
+    best, tune_ms = ctx.autotune(dev, reps=2, stream=stream, cache=False)
+    tuning = ctx.get_tuning().as_dict()
+    run = lambda: ctx.reconstruct(dev, out, stream)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    med, mn = event_times(torch, run, stream)
+    got = out.to_host()
+    k = kernel_ms(ctx, dev, out, stream, 5)
+    alg = algorithmic_bytes(batch, got[0], got[1])
+    ws = sbt.Workspace(E, H)
+    plain_steps = max(3, steps // 4)
+    sbt.sbt_reconstruct(params, dev, out, ws, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(plain_steps):
+        sbt.sbt_reconstruct(params, dev, out, ws, stream)
+    torch.cuda.synchronize()
+    sec_plain = (time.perf_counter() - t0) / plain_steps
+    plain_same = all(np.array_equal(a, b) for a, b in zip(out.to_host()[:3], got[:3]))
+    n = min(E, oracle_events)
+    t0 = time.perf_counter()
+    want = oracle.reconstruct(batch.select(range(n)))
+    cpu_s = time.perf_counter() - t0
+    stats = ctx.graph_stats()
+    ctx.close()
+    del ws
+    achieved = alg / (k[0] * 1e-3) / 1e9
+    return {"workload": WORKLOADS[workload].format(E=E), "n_events": E, "n_hits": H,
+            "events_per_s": round(E / sec, 1), "hits_per_s": round(H / sec, 1), "ms_per_step": round(sec * 1e3, 4),
+            "event_timed_ms": {"median": round(med, 4), "min": round(mn, 4), "runs": 20},
+            "launch": "graph" if stats["replays"] >= steps else "direct",
+            "tuning": tuning, "rule_tuning": rule, "autotune_ms": round(tune_ms, 4),
+            "k_persistent_ms": round(float(k[0]), 4),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBPS, 6), "algorithmic_bytes_per_launch": int(alg)},
+            "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
+                      "equals_batched": bool(plain_same)},
+            "n_tracks": int(got[0][-1]),
+            "oracle_sample": {"events": n, "gpu_matches": sample_matches(got, want, n),
+                              "cpu_events_per_s_1core": round(n / cpu_s, 2)}}
 
 
 def main():
@@ -373,9 +510,12 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end legs (kernel profiles)")
-    ap.add_argument("--tpe", type=int, default=0, help="threads per event (0: autotune)")
-    ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (0: autotune)")
+    ap.add_argument("--no-e2e", action="store_true", help="skip the end-to-end legs")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the mu1-25 and mu30 legs")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="the headline batch alone (graph replays, direct launches, stage timing): for profiles")
+    ap.add_argument("--tpe", type=int, default=0, help="threads per event (0: the library's choice)")
+    ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (with --tpe)")
     ap.add_argument("--cap", type=int, default=672, help="LDS slot capacity in hits (with --tpe/--bpc)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run one elementwise multiply over this many MiB (counter calibration)")
@@ -384,13 +524,23 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so "
               "several GPUs would each run this same per-GPU path on their own events.", file=sys.stderr)
         sys.exit(2)
+    if args.kernel_only:
+        args.no_cpu = args.no_serve = args.no_e2e = args.no_workloads = True
 
     from paper_2207_03936_amd import synth
     batch = synth.make_batch(args.workload, args.events or None)
+    log(f"{args.workload}: {batch.n_events} events, {batch.n_hits} hits")
     cpu_par = None
+    cpu_share = 16       # processes a one-GPU host share runs at once
     if not args.no_cpu:
         # before the GPU is touched: the processes are forked
-        cpu_par = cpu_parallel_baseline(batch, args.workload, min(16, os.cpu_count() or 1))
+        cpu_par = cpu_parallel_baseline(batch, args.workload, min(cpu_share, os.cpu_count() or 1))
+        cpu_par.update(host_cpu())
+        log(f"oracle on {cpu_par['cores']} processes: {cpu_par['value']} events/s")
+    extra = {}
+    if not args.no_workloads:
+        extra = {"mu1-25": synth.make_batch("mu1-25"), "mu30": synth.make_batch("mu30")}
+        log("mu1-25 and mu30 batches generated")
 
     import torch
     from paper_2207_03936_amd import sbt
@@ -402,14 +552,15 @@ def main():
     dev = sbt.DeviceBatch(batch)
     out = sbt.DeviceTracks(E, H)
     ws = sbt.Workspace(E, H)
-    ctx = sbt.Context(params, E, H)
-    if args.tpe and args.bpc:
-        ctx.set_tuning(sbt.make_tuning(args.tpe, args.bpc, args.cap))
-        tuned_ms = None
-    else:
-        best, tuned_ms = ctx.autotune(dev, reps=3, cache=False)
+    # the headline context: the configuration the library chooses for the
+    # batch's size (or one given on the command line)
+    ctx = sbt.Context(params, E, H, sbt.make_tuning(args.tpe, args.bpc, args.cap) if args.tpe else None)
     tuning = ctx.get_tuning().as_dict()
-    stream = torch.cuda.current_stream()
+    # three streams for every multi-stream leg: with the null stream they take the four hardware
+    # queues HIP opens by default, so no two busy streams share a queue
+    extra_streams = [torch.cuda.Stream() for _ in range(3)]
+    gstream = extra_streams[0]        # non-null: the calls capture and replay a graph
+    null = torch.cuda.current_stream()
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -421,58 +572,28 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    # batched: persistent kernel replayed as a captured graph
-    sec_batched = timed(lambda: ctx.reconstruct(dev, out), args.steps, args.warmup)
+    # batched: the persistent kernel and its tail replayed as a captured graph
+    graph_call = lambda: ctx.reconstruct(dev, out, gstream)
+    g0 = ctx.graph_stats()
+    sec_batched = timed(graph_call, args.steps, args.warmup)
+    g1 = ctx.graph_stats()
+    launch = "graph" if g1["replays"] - g0["replays"] >= args.steps and g1["direct"] == g0["direct"] else "direct"
     got = out.to_host()
-    # plain per-event kernels
-    sec_plain = timed(lambda: sbt.sbt_reconstruct(params, dev, out, ws), args.steps, args.warmup)
-    got_plain = out.to_host()
-    same_paths = all(np.array_equal(a, b) for a, b in zip(got[:3], got_plain[:3]))
-    # three streams for every multi-stream leg: with the null stream they take the four hardware
-    # queues HIP opens by default, so no two busy streams share a queue
-    extra_streams = [torch.cuda.Stream() for _ in range(3)]
-    plain_multi = [plain_streams_leg(torch, sbt, params, batch, args.steps, args.warmup, extra_streams[:t])
-                   for t in (2, 3)]
-    # the paper's insertion-rank sort beside the bucket sort (each call: sort kernel + copy-out kernel)
-    sort_ms = {}
-    sort_out = (torch.zeros(H, dtype=torch.int16, device="cuda"), torch.zeros(H, dtype=torch.int16, device="cuda"))
-    for method in ("bucket", "rank"):
-        sec = timed(lambda: sbt.sbt_debug_phi_sort(params, dev, method=method, workspace=ws, out=sort_out,
-                                                   to_host=False), max(5, args.steps // 2), 2)
-        sort_ms[method] = round(sec * 1e3, 4)
+    med_ms, min_ms = event_times(torch, graph_call, gstream)
+    # the same sequence launched directly, on the null stream
+    sec_direct = timed(lambda: ctx.reconstruct(dev, out, null), args.steps, args.warmup)
+    direct_same = all(np.array_equal(a, b) for a, b in zip(out.to_host()[:3], got[:3]))
+    log(f"headline: {sec_batched * 1e3:.4f} ms per batch ({launch}), direct {sec_direct * 1e3:.4f} ms")
 
     # dominant kernel duration: HIP events around the persistent kernel on the
     # stream it is launched on (profiling mode launches without the graph)
-    ctx.set_profiling(True)
-    stage = np.zeros(3)
-    n_prof = max(5, min(args.steps, 20))
-    for _ in range(n_prof):
-        ctx.reconstruct(dev, out, stream)
-        stage += np.array(ctx.stage_ms())
-    stage /= n_prof
-    ctx.set_profiling(False)
+    stage = kernel_ms(ctx, dev, out, gstream, max(5, min(args.steps, 20)))
     k_ms = float(stage[0])
     alg = algorithmic_bytes(batch, got[0], got[1])
     achieved = alg / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic(H)
+    traffic = measured_traffic(H, tuning)
+    sq = measured_sq(H, tuning)
     copy_gbps = copy_bandwidth(torch)
-    sq = measured_sq(H)
-    if not args.no_e2e:
-        e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
-        pipe_streams = extra_streams
-        e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
-                           streams=pipe_streams)
-    # half-precision array-of-structures input (the paper's hit-storage optimisation)
-    dev16 = sbt.DeviceBatchF16(batch)
-    out16 = sbt.DeviceTracks(E, H)
-    sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16), args.steps, args.warmup)
-    got16 = out16.to_host()
-    if not args.no_e2e:
-        e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
-                             streams=pipe_streams)
-        seq_leg = sequence_leg(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)),
-                               pipe_streams)
-    del dev16, out16
 
     result = {
         "metric": "events/s on 1 MI355X at mu=7.6 (batched vs plain) + p99 event latency",
@@ -488,16 +609,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload].format(E=E),
-                   "n_events": E, "n_hits": H, "tuning": tuning},
+                   "n_events": E, "n_hits": H, "tuning": tuning, "launch": launch},
         "hits_per_s": round(H / sec_batched, 1),
-        "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
-                  "hits_per_s": round(H / sec_plain, 1)},
-        "plain_streams": plain_multi,
-        "sort_ablation": {"bucket_sort_call_ms": sort_ms["bucket"], "insertion_rank_sort_call_ms": sort_ms["rank"],
-                          "note": "whole batch; each call is the sort kernel, a copy of the sorted angles and ids, "
-                                  "and for the rank sort a host read of the event offsets"},
-        "batched_over_plain": round(sec_plain / sec_batched, 3),
-        "plain_equals_batched": bool(same_paths),
+        "launch": launch,
+        "graph_stats": g1,
+        "event_timed_ms": {"median": round(med_ms, 4), "min": round(min_ms, 4), "runs": 20},
+        "direct_ms": round(sec_direct * 1e3, 4),
+        "direct_equals_graph": bool(direct_same),
         "stage_ms": {"k_persistent": round(k_ms, 4), "k_scan": round(float(stage[1]), 4),
                      "k_write": round(float(stage[2]), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
@@ -518,6 +636,80 @@ def main():
                           "valu_instructions_per_launch": int(sq["SQ_INSTS_VALU"]),
                           "salu_instructions_per_launch": int(sq["SQ_INSTS_SALU"]),
                           "lds_instructions_per_launch": int(sq["SQ_INSTS_LDS"])}
+    if args.kernel_only:
+        if args.calibrate_copy:
+            calibrate(torch, args.calibrate_copy, result)
+        ctx.close()
+        print(json.dumps(result), flush=True)
+        return
+
+    # plain per-event kernels
+    sec_plain = timed(lambda: sbt.sbt_reconstruct(params, dev, out, ws), args.steps, args.warmup)
+    log(f"plain: {sec_plain * 1e3:.4f} ms per batch")
+    got_plain = out.to_host()
+    same_paths = all(np.array_equal(a, b) for a, b in zip(got[:3], got_plain[:3]))
+    plain_multi = [plain_streams_leg(torch, sbt, params, batch, args.steps, args.warmup, extra_streams[:t])
+                   for t in (2, 3)]
+    # the paper's insertion-rank sort beside the bucket sort (each call: sort kernel + copy-out kernel)
+    sort_ms = {}
+    sort_out = (torch.zeros(H, dtype=torch.int16, device="cuda"), torch.zeros(H, dtype=torch.int16, device="cuda"))
+    for method in ("bucket", "rank"):
+        sec = timed(lambda: sbt.sbt_debug_phi_sort(params, dev, method=method, workspace=ws, out=sort_out,
+                                                   to_host=False), max(5, args.steps // 2), 2)
+        sort_ms[method] = round(sec * 1e3, 4)
+    # the paper's separate candidate pass before seeding, on the plain form
+    sec_fill = timed(lambda: sbt.sbt_debug_reconstruct_fill_candidates(params, dev, out, ws), args.steps,
+                     args.warmup)
+    fill_same = all(np.array_equal(a, b) for a, b in zip(out.to_host()[:3], got[:3]))
+    log(f"plain with the candidate pass: {sec_fill * 1e3:.4f} ms per batch")
+    # the autotuner on the headline batch, in a context of its own
+    tctx = sbt.Context(params, E, H)
+    best, tuned_ms = tctx.autotune(dev, reps=3, stream=gstream, cache=False)
+    tout = sbt.DeviceTracks(E, H)
+    sec_tuned = timed(lambda: tctx.reconstruct(dev, tout, gstream), args.steps, args.warmup)
+    tuned_same = all(np.array_equal(a, b) for a, b in zip(tout.to_host()[:3], got[:3]))
+    autotune = {"tuning": tctx.get_tuning().as_dict(), "autotune_ms": round(tuned_ms, 4),
+                "events_per_s": round(E / sec_tuned, 1), "ms_per_step": round(sec_tuned * 1e3, 4),
+                "equals_headline": bool(tuned_same)}
+    tctx.close()
+    del tout
+    log(f"autotune picked {autotune['tuning']}: {autotune['ms_per_step']} ms")
+    if not args.no_e2e:
+        e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
+        pipe_streams = extra_streams
+        e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
+                           streams=pipe_streams)
+    # half-precision array-of-structures input (the paper's hit-storage optimisation)
+    dev16 = sbt.DeviceBatchF16(batch)
+    out16 = sbt.DeviceTracks(E, H)
+    sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16, gstream), args.steps, args.warmup)
+    got16 = out16.to_host()
+    if not args.no_e2e:
+        e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
+                             streams=pipe_streams)
+        seq_leg = sequence_leg(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)),
+                               pipe_streams)
+    del dev16, out16
+    log("binary16, end-to-end and sequence legs done")
+
+    result.update({
+        "plain": {"events_per_s": round(E / sec_plain, 1), "ms_per_step": round(sec_plain * 1e3, 4),
+                  "hits_per_s": round(H / sec_plain, 1)},
+        "plain_streams": plain_multi,
+        "sort_ablation": {"bucket_sort_call_ms": sort_ms["bucket"], "insertion_rank_sort_call_ms": sort_ms["rank"],
+                          "note": "whole batch; each call is the sort kernel, a copy of the sorted angles and ids, "
+                                  "and for the rank sort a host read of the event offsets"},
+        "fill_candidates_ablation": {"plain_ms": round(sec_plain * 1e3, 4),
+                                     "plain_with_candidate_pass_ms": round(sec_fill * 1e3, 4),
+                                     "fused_over_separate": round(sec_fill / sec_plain, 3),
+                                     "equals_batched": bool(fill_same),
+                                     "note": "plain per-event kernels; the candidate pass writes every hit's "
+                                             "pendulum start before the seeding kernel, which reads it instead "
+                                             "of searching"},
+        "batched_over_plain": round(sec_plain / sec_batched, 3),
+        "plain_equals_batched": bool(same_paths),
+        "autotune": autotune,
+    })
     if not args.no_e2e:
         result["end_to_end"] = e2e
         result["end_to_end_pipelined"] = e2e_p
@@ -528,27 +720,46 @@ def main():
     if not args.no_e2e:
         result["f16_aos"]["end_to_end_pipelined"] = e2e_f16
         result["sequence"] = seq_leg
-    if tuned_ms is not None:
-        result["autotune_ms"] = round(tuned_ms, 4)
+    del ws
+    ctx.close()
+    for name, b in extra.items():
+        result[name] = workload_leg(torch, sbt, b, name, max(5, args.steps // 5), 2, gstream,
+                                    50 if name == "mu1-25" else 20)
+        log(f"{name}: {result[name]['events_per_s']} events/s")
+    extra.clear()
     if not args.no_serve:
-        result["serving"] = serving_leg(params, args.serve_seconds)
+        # algorithmic bytes per event of the serving pool, from one batched call over it
+        pool = synth.make_batch("serve", 2000)
+        pctx = sbt.Context(sbt.make_params(pool.module_z), pool.n_events, pool.n_hits)
+        pgot = pctx.reconstruct(sbt.DeviceBatch(pool)).to_host()
+        pctx.close()
+        per_event = algorithmic_bytes(pool, pgot[0], pgot[1]) / pool.n_events
+        result["serving"] = serving_leg(params, args.serve_seconds, bytes_per_event=per_event)
         result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
+        log(f"serving: p99 {result['serving']['p99_ms']} ms")
         # the same with hits sent to the device as binary16 (results are those
         # of the rounded hits): 80 % of its own burst saturation
-        result["serving_f16"] = serving_leg(params, args.serve_seconds, fraction=0.8, coords_f16=True)
+        result["serving_f16"] = serving_leg(params, args.serve_seconds, fraction=0.8, coords_f16=True,
+                                            bytes_per_event=per_event)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(batch, got, args.workload)
+        result["cpu_baseline"].update(host_cpu())
         result["cpu_baseline_all_cores"] = cpu_par
     if args.calibrate_copy:
-        n = args.calibrate_copy * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)     # one elementwise kernel: reads and writes 4n bytes
-        torch.cuda.synchronize()
-        result["calibration_copy_bytes"] = 4 * n
-    ctx.close()
+        calibrate(torch, args.calibrate_copy, result)
     print(json.dumps(result), flush=True)
+
+
+def calibrate(torch, mib, result):
+    """One elementwise multiply over `mib` MiB, for scaling the fabric
+    counters: it reads and writes 4n bytes."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    result["calibration_copy_bytes"] = 4 * n
 
 
 if __name__ == "__main__":

@@ -270,6 +270,31 @@ int sbt_autotune(sbt_context *ctx, const sbt_hits *sample, sbt_tracks *tracks, v
 int sbt_context_set_profiling(sbt_context *ctx, int32_t on);
 int sbt_context_stage_ms(sbt_context *ctx, float *stage_ms, int32_t n);
 
+/* Graph cache of a context.  sbt_reconstruct_batched on a non-null stream
+ * with profiling off captures the batched sequence once per argument set
+ * (batch size, every device pointer of the hits and the tracks) and replays
+ * the instantiated graph on later calls with the same set; at most
+ * `capacity` graphs are kept, the least recently used one is evicted.  On
+ * the null stream or with profiling on, the kernels are launched directly.
+ *   cached     graphs in the cache now
+ *   capacity   most graphs kept (8)
+ *   captures   graphs captured and instantiated (each launched once at once)
+ *   replays    calls served by a graph already in the cache
+ *   evictions  graphs dropped to make room (sbt_context_set_tuning clears
+ *              the cache without counting evictions)
+ *   direct     calls launched without a graph
+ * Host-side counters only; returns SBT_OK or SBT_ERR_INVALID_ARG.        */
+typedef struct sbt_graph_stats {
+    int32_t cached;
+    int32_t capacity;
+    int64_t captures;
+    int64_t replays;
+    int64_t evictions;
+    int64_t direct;
+} sbt_graph_stats;
+
+int sbt_context_graph_stats(const sbt_context *ctx, sbt_graph_stats *out);
+
 /* ---- inspection ----------------------------------------------------------------
  * Run only the phi sort of the plain form and copy its result: for every
  * hit position p of the batch (module by module, phi16 ascending, ties by
@@ -287,6 +312,19 @@ int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t 
 int sbt_debug_phi_sort_rank(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted,
                             uint16_t *ids_sorted, void *workspace, size_t workspace_bytes,
                             void *stream);
+
+/* The plain form with the paper's separate candidate pass, for comparison
+ * with the fused search (Section 4, optimisation table: a "Fill candidates"
+ * kernel was split from the tracklet filter and later removed; the paper
+ * does not say what it computes).  Reading taken here: the pass computes,
+ * for every hit of every module but the first in traversal order, the part of
+ * the doublet search that does not depend on the flags -- its pendulum start,
+ * the first position of the preceding module whose phi16 is >= the hit's
+ * (0 when there is none) -- and writes it into the workspace; the seeding
+ * kernel then reads the start instead of searching for it.  Same arguments,
+ * errors and outputs as sbt_reconstruct, byte for byte.                    */
+int sbt_debug_reconstruct_fill_candidates(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks,
+                                          void *workspace, size_t workspace_bytes, void *stream);
 
 /* The host conversion of the server's binary16 transfer: n hits from binary32
  * x, y, z (HOST memory) to the 8-byte records of sbt_hits_f16 (x, y, z, 0;
@@ -394,7 +432,12 @@ int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_res
  * server is polled continuously, its hits read in place (the pool must stay
  * unchanged during the call).  Writes each arrival's latency (result visible
  * on the host minus its arrival time) into latency_us[i], its track count
- * into n_tracks[i] (may be NULL), and the wall time into *wall_us.      */
+ * into n_tracks[i] (may be NULL), and the wall time into *wall_us.
+ * The server must be idle (nothing queued, on the device or uncollected;
+ * see sbt_server_pending): otherwise SBT_ERR_NOT_READY, since results are
+ * matched to arrivals by request id.  SBT_ERR_INVALID_ARG for a pick outside
+ * the pool or negative event size, SBT_ERR_EVENT_TOO_LARGE for an event of
+ * more than 65,535 hits; both are checked before the first submission.   */
 int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival_us, const int32_t *picks,
                       int32_t pool_events, const int32_t *event_offsets, const int32_t *module_offsets,
                       const float *x, const float *y, const float *z,

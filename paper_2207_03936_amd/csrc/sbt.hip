@@ -81,7 +81,7 @@ __global__ __launch_bounds__(B) void k_phi_sort_rank(sbt_params P, HitsArgs H, W
     }
 }
 
-template <int B, int CAP>
+template <int B, int CAP, bool kCand>
 __global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Work W, int own_cap)
 {
     __shared__ Shared<B> S;
@@ -89,8 +89,21 @@ __global__ __launch_bounds__(B) void k_seed_follow(sbt_params P, HitsArgs H, Wor
     if (ws_evinfo(W)[e].st != 0) return;
     int hb, N;
     load_event<B>(P, H, e, S, &hb, &N);
-    stage_track<B, CAP>(P, event_view(W, e, hb, N), S, own_cap, true);
+    stage_track<B, CAP, kCand>(P, event_view(W, e, hb, N), S, own_cap, true);
     if (threadIdx.x == 0) ws_evinfo(W)[e].nfin = S.cnt[3];
+}
+
+// The paper's separate candidate pass (ablation): the pendulum start of every
+// hit, written before the seeding kernel runs.
+template <int B>
+__global__ __launch_bounds__(B) void k_fill_candidates(sbt_params P, HitsArgs H, Work W)
+{
+    __shared__ Shared<B> S;
+    const int e = blockIdx.x;
+    if (ws_evinfo(W)[e].st != 0) return;
+    int hb, N;
+    load_event<B>(P, H, e, S, &hb, &N);
+    stage_fill_candidates<B>(P, event_view(W, e, hb, N), S);
 }
 
 template <int B>
@@ -459,12 +472,18 @@ OutArgs out_args(const sbt_tracks *t)
         if ((expr) != hipSuccess) return SBT_ERR_HIP;   \
     } while (0)
 
-int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hipStream_t s)
+int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hipStream_t s,
+                       bool fill_candidates = false)
 {
     const dim3 g(H.n_events), b(kPlainThreads);
     const uint32_t lds = lds_bytes(kPlainCap, kPlainOwnCap);
     hipLaunchKernelGGL(k_phi_sort<kPlainThreads>, g, b, lds, s, P, H, W, lds_sortcap(kPlainCap, kPlainOwnCap));
-    hipLaunchKernelGGL((k_seed_follow<kPlainThreads, kPlainCap>), g, b, lds, s, P, H, W, kPlainOwnCap);
+    if (fill_candidates) {
+        hipLaunchKernelGGL(k_fill_candidates<kPlainThreads>, g, b, 0, s, P, H, W);
+        hipLaunchKernelGGL((k_seed_follow<kPlainThreads, kPlainCap, true>), g, b, lds, s, P, H, W, kPlainOwnCap);
+    } else {
+        hipLaunchKernelGGL((k_seed_follow<kPlainThreads, kPlainCap, false>), g, b, lds, s, P, H, W, kPlainOwnCap);
+    }
     hipLaunchKernelGGL(k_weak_filter<kPlainThreads>, g, b, 0, s, P, H, W);
     hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, 0, s, H, W);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
@@ -668,6 +687,27 @@ int sbt_reconstruct(const sbt_params *params, const sbt_hits *hits, sbt_tracks *
     return launch_tail(H, W, O, s);
 }
 
+int sbt_debug_reconstruct_fill_candidates(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks,
+                                          void *workspace, size_t workspace_bytes, void *stream)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const HitsArgs H = hits_args(hits);
+    const OutArgs O = out_args(tracks);
+    if (H.n_events == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
+        return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255)) return SBT_ERR_INVALID_ARG;
+    if (workspace_bytes < carve(H.n_events, H.n_hits, nullptr, nullptr)) return SBT_ERR_WORKSPACE;
+    Work W;
+    carve(H.n_events, H.n_hits, (char *)workspace, &W);
+    if ((rc = launch_plain_front(*params, H, W, s, true))) return rc;
+    return launch_tail(H, W, O, s);
+}
+
 int sbt_debug_phi_sort(const sbt_params *params, const sbt_hits *hits, uint16_t *phi_sorted, uint16_t *ids_sorted,
                        void *workspace, size_t workspace_bytes, void *stream)
 {
@@ -782,6 +822,7 @@ struct sbt_context {
     int have_marks;
     int per_launch;   // created without a tuning: chosen per call from the batch's size
     int cus;          // compute units of the device the context was created on
+    int64_t captures, replays, evictions, direct;   // graph cache counters
 };
 
 namespace {
@@ -863,6 +904,7 @@ int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning, int32
     c->max_hits = max_hits;
     c->workspace_bytes = carve(max_events, max_hits, nullptr, nullptr);
     c->clock = 0;
+    c->captures = c->replays = c->evictions = c->direct = 0;
     c->profiling = 0;
     c->have_marks = 0;
     c->per_launch = tuning == nullptr;
@@ -928,6 +970,18 @@ int sbt_context_set_profiling(sbt_context *c, int32_t on)
     return SBT_OK;
 }
 
+int sbt_context_graph_stats(const sbt_context *c, sbt_graph_stats *out)
+{
+    if (!c || !out) return SBT_ERR_INVALID_ARG;
+    out->cached = (int32_t)c->graphs.size();
+    out->capacity = (int32_t)kMaxGraphs;
+    out->captures = c->captures;
+    out->replays = c->replays;
+    out->evictions = c->evictions;
+    out->direct = c->direct;
+    return SBT_OK;
+}
+
 int sbt_context_stage_ms(sbt_context *c, float *ms, int32_t n)
 {
     if (!c || !ms || n < 1) return SBT_ERR_INVALID_ARG;
@@ -956,6 +1010,7 @@ int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
     if (c->profiling || s == nullptr) {
         rc = launch_batched(c->params, T, H, c->W, O, s, c->profiling ? c->marks : nullptr);
         if (rc == SBT_OK && c->profiling) c->have_marks = 1;
+        if (rc == SBT_OK) ++c->direct;
         return rc;
     }
     std::vector<uintptr_t> key = {
@@ -967,6 +1022,7 @@ int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
         if (g.key == key) {
             g.last_use = c->clock;
             HIP_TRY(hipGraphLaunch(g.exec, s));
+            ++c->replays;
             return SBT_OK;
         }
     }
@@ -987,8 +1043,10 @@ int batched(sbt_context *c, const HitsArgs &H, sbt_tracks *tracks, void *stream)
                                        [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
         (void)hipGraphExecDestroy(victim->exec);
         c->graphs.erase(victim);
+        ++c->evictions;
     }
     c->graphs.push_back(GraphEntry{key, exec, c->clock});
+    ++c->captures;
     HIP_TRY(hipGraphLaunch(exec, s));
     return SBT_OK;
 }

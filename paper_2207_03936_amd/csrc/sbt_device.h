@@ -1055,7 +1055,9 @@ __device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t p
 }
 
 // Seeding(t), t >= 2 (Section 3), fused with the following search into
-// t+1.  Seeding: modules A = kmod(t-2), Bm = kmod(t-1), C = kmod(t); work
+// t+1.  With kCand the pendulum start of every middle hit is read from the
+// table a separate candidate pass wrote into the workspace (the paper's
+// "Fill candidates" kernel) instead of being searched here.  Seeding: modules A = kmod(t-2), Bm = kmod(t-1), C = kmod(t); work
 // items are (unflagged middle hit, partner rank c) -- with K a power of two
 // up to 16, the K doublets of a middle hit run on K adjacent lanes and their
 // best triplets are reduced across the lanes, otherwise one lane handles all
@@ -1063,7 +1065,7 @@ __device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t p
 // The tracks kept by the last resolution (active slots [0, n_keep)) search
 // t+1 on waves of their own.  Both read the flags as the resolution of t
 // left them, which is the state the following of t+1 starts from.
-template <int B, bool kLds, int CAP>
+template <int B, bool kLds, int CAP, bool kCand = false>
 __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Shared<B> &S, const uint32_t *own,
                                   uint16_t *nxt, int *n_nxt, int n_keep, bool follow_next)
 {
@@ -1157,8 +1159,13 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
         if (g < seed_items) {
             const int p1 = at(FM, i);
             h1 = at(wb.h, p1);
-            int s0 = win_lower_bound<kLds>(wa, q_of(h1));
-            if (s0 == na) s0 = 0;
+            int s0;
+            if (kCand) {
+                s0 = (int)at(v.keys(), (uint32_t)(uni(S.mo[kmod(P, t - 1)]) + p1));
+            } else {
+                s0 = win_lower_bound<kLds>(wa, q_of(h1));
+                if (s0 == na) s0 = 0;
+            }
             const int j = at(FR, s0);   // first unflagged position >= s0, as an index into F
             if (G == 4) {
                 const int pos0 = pendulum_quad(F, nf, j, s0, na, hu, hd, c);
@@ -1315,7 +1322,7 @@ __device__ __forceinline__ bool event_fits_lds(const Shared<B> &S, int N, int ow
 // the final list and its length in S.cnt[3]; with writeback the LDS flags are
 // copied to memory.  The LDS instantiation returns false when an active list
 // outgrew its LDS capacity (the event is then run again from memory).
-template <int B, bool kLds, int CAP>
+template <int B, bool kLds, int CAP, bool kCand = false>
 __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S, bool writeback)
 {
     const Prm P = fresh(PP);
@@ -1348,7 +1355,7 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
     }
     last_seed = uni(last_seed);
     int par = 0;
-    stage_seed_follow<B, kLds, CAP>(PP, v, 2, S, own, l0, &S.cnt[1], 0, M > 3);
+    stage_seed_follow<B, kLds, CAP, kCand>(PP, v, 2, S, own, l0, &S.cnt[1], 0, M > 3);
     __syncthreads();
     if (kLds && uni(S.ovf)) return false;
     for (int t = 3; t < M; ++t) {
@@ -1375,7 +1382,7 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
         const int n_keep = uni(S.cnt[1 + (par ^ 1)]);
         if (threadIdx.x == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
         if (!(kLds && uni(S.ovf)))
-            stage_seed_follow<B, kLds, CAP>(PP, v, t, S, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
+            stage_seed_follow<B, kLds, CAP, kCand>(PP, v, t, S, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
         __syncthreads();
         if (kLds && uni(S.ovf)) return false;
         par ^= 1;
@@ -1394,16 +1401,44 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
 }
 
 // Runs the tracking stages; returns true when the event's flags ended in LDS.
-template <int B, int CAP>
+template <int B, int CAP, bool kCand = false>
 __device__ bool stage_track(const sbt_params &P, const Ev &v, Shared<B> &S, int own_cap, bool writeback)
 {
     if constexpr (CAP > 0) {
         if (event_fits_lds<B, CAP>(S, v.N, own_cap)) {
-            if (stage_track_impl<B, true, CAP>(P, v, S, writeback)) return true;
+            if (stage_track_impl<B, true, CAP, kCand>(P, v, S, writeback)) return true;
         }
     }
-    stage_track_impl<B, false, CAP>(P, v, S, false);
+    stage_track_impl<B, false, CAP, kCand>(P, v, S, false);
     return false;
+}
+
+// ---------------------------------------------------------------- candidate pass
+// The paper's separate "Fill candidates" step, as an ablation of the fused
+// search: for every hit of every module after the first in traversal order,
+// the first position of the preceding module (in traversal order: the
+// doublet module when this hit is a middle hit) whose phi16 is >= the hit's,
+// 0 when there is none -- the pendulum start, which does not depend on the
+// flags.  Written by sorted position into the keys array (free after the
+// sort) for the seeding stage to read.
+template <int B>
+__device__ void stage_fill_candidates(const sbt_params &PP, const Ev &v0, const Shared<B> &S)
+{
+    const Ev v = fresh(v0);
+    const Prm P = fresh(PP);
+    for (int u = 1; u < P.M; ++u) {
+        const int k = kmod(P, u), ka = kmod(P, u - 1);
+        const int g0 = S.mo[k], n = S.mo[k + 1] - g0;
+        Win wa;
+        wa.h = v.hs() + S.mo[ka];
+        wa.n = S.mo[ka + 1] - S.mo[ka];
+        wa.tab = nullptr;
+        for (int i = threadIdx.x; i < n; i += B) {
+            int s0 = wa.n > 0 ? win_lower_bound<false>(wa, q_of(at(v.hs(), (uint32_t)(g0 + i)))) : 0;
+            if (s0 == wa.n) s0 = 0;
+            at(v.keys(), (uint32_t)(g0 + i)) = (uint32_t)s0;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- tracklet filter

@@ -650,8 +650,17 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
         !x || !y || !z || !latency_us || !wall_us)
         return SBT_ERR_INVALID_ARG;
     const int M = srv->params.n_modules;
-    for (int32_t i = 0; i < n_arrivals; ++i)
+    // results are indexed by arrival, so nothing submitted earlier may still
+    // be pending: its request id could be any value
+    int32_t queued = 0, in_flight = 0;
+    sbt_server_pending(srv, &queued, &in_flight);
+    if (queued != 0 || in_flight != 0) return SBT_ERR_NOT_READY;
+    for (int32_t i = 0; i < n_arrivals; ++i) {
         if (picks[i] < 0 || picks[i] >= pool_events) return SBT_ERR_INVALID_ARG;
+        const int32_t n = event_offsets[picks[i] + 1] - event_offsets[picks[i]];
+        if (n < 0) return SBT_ERR_INVALID_ARG;
+        if (n > SBT_MAX_EVENT_HITS) return SBT_ERR_EVENT_TOO_LARGE;
+    }
     std::vector<sbt_server_result> res(512);
     const double t0 = now_us();
     int32_t next = 0, done = 0;
@@ -660,7 +669,6 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
         while (next < n_arrivals && arrival_us[next] <= t && srv->queue.size() < srv->max_queue) {
             const int32_t e = picks[next];
             const int32_t lo = event_offsets[e], hi = event_offsets[e + 1];
-            if (hi - lo > SBT_MAX_EVENT_HITS || hi < lo) return SBT_ERR_EVENT_TOO_LARGE;
             QueuedEvent q;
             q.id = next;
             q.t_submit = t0 + arrival_us[next];
@@ -676,6 +684,7 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
         if (n < 0) return n;
         for (int i = 0; i < n; ++i) {
             const int64_t id = res[(size_t)i].request_id;
+            if (id < 0 || id >= n_arrivals) return SBT_ERR_INVALID_ARG;   // never expected: the server was idle
             latency_us[id] = res[(size_t)i].t_done_us - (t0 + arrival_us[id]);
             if (n_tracks) n_tracks[id] = res[(size_t)i].n_tracks;
             ++done;

@@ -92,6 +92,14 @@ class SbtTuning(ctypes.Structure):
                     lds_window_hits=self.lds_window_hits, lds_owner_hits=self.lds_owner_hits)
 
 
+class SbtGraphStats(ctypes.Structure):
+    _fields_ = [("cached", ctypes.c_int32), ("capacity", ctypes.c_int32), ("captures", ctypes.c_int64),
+                ("replays", ctypes.c_int64), ("evictions", ctypes.c_int64), ("direct", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 class SbtServerConfig(ctypes.Structure):
     _fields_ = [("device_budget_bytes", ctypes.c_size_t), ("n_slots", ctypes.c_int32),
                 ("slot_events", ctypes.c_int32), ("slot_hits", ctypes.c_int32),
@@ -125,6 +133,9 @@ PROTOTYPES = {
                                     _P(ctypes.c_float)]),
     "sbt_context_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "sbt_context_stage_ms": (ctypes.c_int, [_VP, _P(ctypes.c_float), ctypes.c_int32]),
+    "sbt_context_graph_stats": (ctypes.c_int, [_VP, _P(SbtGraphStats)]),
+    "sbt_debug_reconstruct_fill_candidates": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _P(SbtTracks), _VP,
+                                                             ctypes.c_size_t, _VP]),
     "sbt_debug_phi_sort": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "sbt_debug_phi_sort_rank": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _VP, _VP, _VP, ctypes.c_size_t, _VP]),
     "sbt_debug_half_records": (ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int32, _VP]),
@@ -346,6 +357,20 @@ def sbt_reconstruct(params: SbtParams, batch: DeviceBatch, out: Optional[DeviceT
     return out
 
 
+def sbt_debug_reconstruct_fill_candidates(params: SbtParams, batch: DeviceBatch, out: Optional[DeviceTracks] = None,
+                                          workspace: Optional[Workspace] = None, stream=None) -> DeviceTracks:
+    """The plain per-event kernels with the separate candidate pass before
+    seeding (asynchronous on torch's current stream)."""
+    out = out or DeviceTracks(batch.n_events, batch.n_hits)
+    ws = workspace or Workspace(batch.n_events, batch.n_hits)
+    _check(lib().sbt_debug_reconstruct_fill_candidates(ctypes.byref(params), ctypes.byref(batch.hits),
+                                                       ctypes.byref(out.tracks), ctypes.c_void_p(ws.ptr), ws.bytes,
+                                                       _stream_handle(stream)),
+           "sbt_debug_reconstruct_fill_candidates")
+    out._keep = ws
+    return out
+
+
 def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None, method: str = "bucket",
                        workspace: Optional[Workspace] = None, out=None, to_host: bool = True):
     """(phi16, ids) of every hit position after the per-module phi sort;
@@ -447,6 +472,12 @@ class Context:
         arr = (ctypes.c_float * 3)()
         _check(lib().sbt_context_stage_ms(self.handle, arr, 3), "sbt_context_stage_ms")
         return [float(v) for v in arr]
+
+    def graph_stats(self) -> dict:
+        """The graph cache's counters (sbt_context_graph_stats)."""
+        st = SbtGraphStats()
+        _check(lib().sbt_context_graph_stats(self.handle, ctypes.byref(st)), "sbt_context_graph_stats")
+        return st.as_dict()
 
     def reconstruct(self, batch: DeviceBatch, out: Optional[DeviceTracks] = None, stream=None) -> DeviceTracks:
         out = out or DeviceTracks(batch.n_events, batch.n_hits)

@@ -4,8 +4,9 @@ Events are drawn from the serving recipe (per-event pileup mu ~ U{1..25},
 seed 5) into a pool of distinct events; arrival i is a uniformly chosen pool
 event submitted at its Poisson arrival time by the library's replay driver,
 which polls the server continuously.  Latency is the time from an event's
-arrival to its tracks being visible on the host (queueing, H2D copy,
-reconstruction, D2H copy and collection included).
+arrival to its tracks being visible on the host (queueing, staging of the
+hits in pinned memory, H2D copy, reconstruction whose last kernel writes the
+tracks into pinned host memory, and collection included).
 
     python -m paper_2207_03936_amd.serve_bench --rates 0.25,0.5,0.8,0.95 --seconds 60
 
@@ -53,8 +54,9 @@ def run_rate(srv, pool, rate, seconds, seed=123, max_events=2_000_000):
 
 def saturation(srv, pool, max_events):
     """Saturated throughput: every arrival at time zero.  A discarded first
-    pass of up to 20,000 events warms the server (result blocks, graphs,
-    host threads), which otherwise shows as a lower first figure."""
+    pass of up to 20,000 events warms the server (result blocks, staging
+    threads, the kernels' first launches), which otherwise shows as a lower
+    first figure."""
     run_rate(srv, pool, 0, 0, max_events=min(20_000, max_events))
     return run_rate(srv, pool, 0, 0, max_events=max_events)
 

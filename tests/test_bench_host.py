@@ -37,13 +37,35 @@ def test_algorithmic_bytes_counts_inputs_and_outputs():
     assert len(th) == int(tho[T]) <= H
 
 
-def test_counter_summaries_follow_the_kernel_source(monkeypatch):
-    path = os.path.join(ROOT, "profiles", "k_persistent_mu7.6_x1000_traffic.json")
-    with open(path) as f:
-        d = json.load(f)
-    monkeypatch.setattr(bench, "kernel_source_hash", lambda: d["kernel_source_hash"])
-    assert bench.measured_traffic(d["n_hits"]) == d["hbm_bytes_per_launch"]
-    assert bench.measured_traffic(d["n_hits"] + 1) is None
+def test_counter_summaries_follow_the_kernel_source_and_tuning(monkeypatch, tmp_path):
+    """A summary is used only for the kernel source, batch size and launch
+    configuration it was taken on."""
+    tuning = dict(threads_per_event=512, blocks_per_cu=2, lds_window_hits=672, lds_owner_hits=16384)
+    d = {"kernel_source_hash": "ab" * 8, "n_hits": 1234, "tuning": dict(tuning),
+         "fabric_bytes_per_launch": 777, "SQ_INSTS_VALU": 5, "SQ_INSTS_SALU": 6, "SQ_INSTS_LDS": 7}
+    (tmp_path / "profiles").mkdir()
+    for name in ("k_persistent_mu7.6_x1000_traffic.json", "k_persistent_mu7.6_x1000_sq.json"):
+        (tmp_path / "profiles" / name).write_text(json.dumps(d))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "ab" * 8)
+    assert bench.measured_traffic(1234, tuning) == 777
+    assert bench.measured_sq(1234, tuning)["SQ_INSTS_VALU"] == 5
+    assert bench.measured_traffic(1235, tuning) is None
+    for k, v in (("threads_per_event", 1024), ("blocks_per_cu", 1), ("lds_window_hits", 768)):
+        other = dict(tuning, **{k: v})
+        assert bench.measured_traffic(1234, other) is None, k
+        assert bench.measured_sq(1234, other) is None, k
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
-    assert bench.measured_traffic(d["n_hits"]) is None
-    assert bench.measured_sq(d["n_hits"]) is None
+    assert bench.measured_traffic(1234, tuning) is None
+    assert bench.measured_sq(1234, tuning) is None
+
+
+def test_committed_summaries_name_their_tuning():
+    """Every committed counter summary records the launch configuration it
+    was taken on, so bench.py can tell whether it describes the timed one."""
+    for name in ("k_persistent_mu7.6_x1000_traffic.json", "k_persistent_mu7.6_x1000_sq.json"):
+        path = os.path.join(ROOT, "profiles", name)
+        with open(path) as f:
+            d = json.load(f)
+        assert set(bench.TUNING_KEYS) <= set(d["tuning"]), name
+        assert "kernel" in d and "commands" in d, name

@@ -63,6 +63,38 @@ def run_batched(batch, tuning=None, **kw):
     return out
 
 
+def graph_replays(ctx, dev, out, stream, reps=3, f16=False):
+    """The batched call on a non-null stream (captured once, then replayed
+    from the context's graph cache), `reps` times; before each call the
+    outputs are overwritten on the same stream, and after it the stream is
+    synchronised and the outputs read back.  Returns every call's outputs
+    and the cache counters after each call."""
+    import torch
+    got, stats = [], []
+    for _ in range(reps):
+        with torch.cuda.stream(stream):
+            out.fill_(-1)
+            if f16:
+                ctx.reconstruct_f16(dev, out, stream)
+            else:
+                ctx.reconstruct(dev, out, stream)
+        stream.synchronize()
+        got.append(out.to_host())
+        stats.append(ctx.graph_stats())
+    return got, stats
+
+
+def check_replays(got, stats, want, what, captures0=0, replays0=0):
+    """Every call equals the oracle; the first was captured, the others
+    came from the cache."""
+    for i, g in enumerate(got):
+        _same(g, want, f"{what} graph call {i}")
+    assert stats[0]["captures"] == captures0 + 1, stats
+    for i, st in enumerate(stats):
+        assert st["captures"] == captures0 + 1 and st["replays"] == replays0 + i, stats
+        assert st["direct"] == stats[0]["direct"], stats
+
+
 # ------------------------------------------------------------------ phi sort
 
 @pytest.mark.parametrize("method", ["bucket", "rank"])
@@ -99,6 +131,9 @@ def test_plain_matches_oracle(config, n):
 
 @pytest.mark.parametrize("config,n", CASES)
 def test_batched_matches_oracle(config, n):
+    """Direct launch on the null stream, then the captured graph on a stream
+    of its own: three calls, the last two replayed from the cache."""
+    import torch
     say(f"batched {config} x{n}")
     b = synth.make_batch(config, n)
     want = oracle.reconstruct(b)
@@ -106,6 +141,58 @@ def test_batched_matches_oracle(config, n):
     assert not got[3].any()
     assert _first_diff(got, want) is None, _first_diff(got, want)
     _same(got, want, f"batched {config}")
+    say(f"batched {config} x{n}: graph replays")
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    dev = sbt.DeviceBatch(b)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    got, stats = graph_replays(ctx, dev, out, torch.cuda.Stream())
+    assert not any(g[3].any() for g in got)
+    check_replays(got, stats, want, f"batched {config}")
+    ctx.close()
+
+
+def test_graph_cache_eviction():
+    """More argument sets than the cache holds: the least recently used
+    graphs are evicted, an evicted set is captured again, a cached one is
+    replayed, and every call gives the oracle's tracks."""
+    import torch
+    say("graph cache eviction")
+    b = synth.make_batch("mu7.6", 12, first=40)
+    want = oracle.reconstruct(b)
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    dev = sbt.DeviceBatch(b)
+    st = torch.cuda.Stream()
+    cap = ctx.graph_stats()["capacity"]
+    outs = [sbt.DeviceTracks(b.n_events, b.n_hits) for _ in range(cap + 2)]
+
+    def call(k):
+        with torch.cuda.stream(st):
+            outs[k].fill_(-1)
+            ctx.reconstruct(dev, outs[k], st)
+        st.synchronize()
+        _same(outs[k].to_host(), want, f"argument set {k}")
+    for k in range(cap + 2):          # distinct output buffers: distinct argument sets
+        call(k)
+    s = ctx.graph_stats()
+    assert (s["cached"], s["captures"], s["replays"], s["evictions"]) == (cap, cap + 2, 0, 2), s
+    call(cap + 1)                     # most recent: replayed
+    s = ctx.graph_stats()
+    assert (s["captures"], s["replays"], s["evictions"]) == (cap + 2, 1, 2), s
+    call(0)                           # evicted first: captured again, evicting the next oldest
+    s = ctx.graph_stats()
+    assert (s["cached"], s["captures"], s["replays"], s["evictions"]) == (cap, cap + 3, 1, 3), s
+    call(0)
+    s = ctx.graph_stats()
+    assert (s["captures"], s["replays"]) == (cap + 3, 2), s
+    # a new configuration drops the cache; the same set is then captured anew
+    ctx.set_tuning(sbt.make_tuning(256, 3, 448))
+    assert ctx.graph_stats()["cached"] == 0
+    call(0)
+    s = ctx.graph_stats()
+    assert (s["cached"], s["captures"]) == (1, cap + 4), s
+    ctx.close()
 
 
 @pytest.mark.parametrize("tpe", [64, 128, 256, 512, 1024])
@@ -274,7 +361,10 @@ def _invariants(b, got):
 
 def test_full_mu7_6_batch_all_events():
     """The 1,000-event mu = 7.6 batch in the launch configuration the
-    benchmark times: every event against the oracle, plain and batched."""
+    benchmark times (chosen per call, graph replays on a stream of its own):
+    every event against the oracle, plain, direct batched launch, and three
+    graph calls (capture, then two replays from the cache)."""
+    import torch
     say("full mu7.6 x1000")
     b = synth.make_batch("mu7.6")
     want = oracle.reconstruct(b)
@@ -283,12 +373,14 @@ def test_full_mu7_6_batch_all_events():
     _same(sbt.sbt_reconstruct(p, dev).to_host(), want, "plain mu7.6 x1000")
     ctx = sbt.Context(p, b.n_events, b.n_hits)
     out = sbt.DeviceTracks(b.n_events, b.n_hits)
-    for rep in range(3):       # graph capture, then replays with eager work between
-        say(f"  batched replay {rep}")
-        out.fill_(-1)
-        ctx.reconstruct(dev, out)
-        got = out.to_host()
-        _same(got, want, f"batched mu7.6 x1000 replay {rep}")
+    say("  batched, direct launch")
+    out.fill_(-1)
+    ctx.reconstruct(dev, out)
+    _same(out.to_host(), want, "batched mu7.6 x1000 direct")
+    assert ctx.graph_stats()["direct"] == 1
+    say("  batched, graph replays")
+    got, stats = graph_replays(ctx, dev, out, torch.cuda.Stream())
+    check_replays(got, stats, want, "batched mu7.6 x1000")
     ctx.close()
 
 
@@ -323,6 +415,9 @@ def test_f16_independent_of_launch_configuration(tpe, cap):
 
 
 def test_f16_full_mu7_6_batch():
+    """Binary16 input on the full mu = 7.6 batch: a direct launch, then three
+    graph calls on a stream of their own."""
+    import torch
     say("f16 full mu7.6 x1000")
     b = synth.make_batch("mu7.6")
     want = oracle.reconstruct(rounded_to_f16(b))
@@ -330,10 +425,11 @@ def test_f16_full_mu7_6_batch():
     ctx = sbt.Context(p, b.n_events, b.n_hits)
     dev = sbt.DeviceBatchF16(b)
     out = sbt.DeviceTracks(b.n_events, b.n_hits)
-    for rep in range(2):
-        out.fill_(-1)
-        ctx.reconstruct_f16(dev, out)
-        _same(out.to_host(), want, f"f16 mu7.6 x1000 replay {rep}")
+    out.fill_(-1)
+    ctx.reconstruct_f16(dev, out)
+    _same(out.to_host(), want, "f16 mu7.6 x1000 direct")
+    got, stats = graph_replays(ctx, dev, out, torch.cuda.Stream(), f16=True)
+    check_replays(got, stats, want, "f16 mu7.6 x1000")
     ctx.close()
 
 
@@ -528,3 +624,73 @@ def test_fewest_and_most_modules(M):
     for tuning in (None, sbt.make_tuning(64, 4, 256), sbt.make_tuning(1024, 1, 1536)):
         _same(run_batched(b, tuning), want, f"batched M={M} {tuning and tuning.as_dict()}")
     _same(run_plain(b, reverse=0), oracle.reconstruct(b, reverse=0), f"plain forward M={M}")
+
+
+def test_autotune_installs_a_candidate_and_keeps_results():
+    """sbt_autotune on a 40-event sample installs one of its candidate
+    configurations; the next calls (a graph capture and a replay on a stream
+    of their own) give the oracle's tracks on the full sample and on another
+    batch through the same context."""
+    import torch
+    say("autotune on 40 events")
+    b = synth.make_batch("mu7.6", 40, first=200)
+    other = synth.make_batch("mu1-25", 25, first=60)
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events + other.n_events, b.n_hits + other.n_hits)
+    dev = sbt.DeviceBatch(b)
+    stream = torch.cuda.Stream()
+    best, ms = ctx.autotune(dev, reps=2, stream=stream, cache=False)
+    t = ctx.get_tuning()
+    say(f"  picked {t.as_dict()} at {ms:.3f} ms")
+    assert t.as_dict() == best.as_dict()
+    assert t.threads_per_event in (128, 256, 512, 1024)
+    assert t.lds_window_hits in (256, 448, 672, 768, 1024, 1536)
+    assert 1 <= t.blocks_per_cu <= 16 and t.lds_owner_hits == 16384
+    assert ms > 0
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    got, stats = graph_replays(ctx, dev, out, stream, reps=2)
+    check_replays(got, stats, oracle.reconstruct(b), "autotuned")
+    dev2 = sbt.DeviceBatch(other)
+    out2 = sbt.DeviceTracks(other.n_events, other.n_hits)
+    got2, _ = graph_replays(ctx, dev2, out2, stream, reps=1)
+    _same(got2[0], oracle.reconstruct(other), "autotuned, another batch")
+    ctx.close()
+
+
+@pytest.mark.parametrize("config,n", [("tiny", 20), ("mu7.6", 40), ("mu1-25", 30), ("mu30", 6), ("pairs7.6", 20),
+                                      ("bw7.6", 20)])
+def test_fill_candidates_pass_matches_oracle(config, n):
+    """The plain form with the separate candidate pass (the paper's Fill
+    candidates kernel, as an ablation) gives the oracle's tracks."""
+    say(f"fill candidates {config} x{n}")
+    b = synth.make_batch(config, n)
+    p = sbt.make_params(b.module_z)
+    got = sbt.sbt_debug_reconstruct_fill_candidates(p, sbt.DeviceBatch(b)).to_host()
+    assert not got[3].any()
+    _same(got, oracle.reconstruct(b), f"fill candidates {config}")
+
+
+def test_fill_candidates_pass_random_parameters():
+    """The candidate pass on crowded tiny events with random parameters and
+    both traversal directions (the pendulum start must not depend on them
+    beyond the traversal order)."""
+    rng = np.random.default_rng(99)
+    for i in range(8):
+        evs = [tiny_random_event(rng, M=6, jitter_z=bool(i % 2)) for _ in range(8)]
+        b = synth.concat([dict(x=x, y=y, z=z, module_counts=np.diff(mo).astype(np.int64),
+                               truth=np.full(len(x), -1, np.int32)) for (x, y, z, mo, mz) in evs], evs[0][4])
+        kw = dict(reverse=int(rng.integers(0, 2)), max_doublet_candidates=int(rng.choice([1, 2, 4, 64])),
+                  phi_window_seeding=int(rng.choice([20, 416, 32767])),
+                  max_consecutive_misses=int(rng.choice([0, 1, 2])))
+        say(f"fill candidates random batch {i} {kw}")
+        p = sbt.make_params(b.module_z, **kw)
+        got = sbt.sbt_debug_reconstruct_fill_candidates(p, sbt.DeviceBatch(b)).to_host()
+        _same(got, oracle.reconstruct(b, **kw), f"fill candidates random {i}")
+
+
+def test_fill_candidates_full_mu7_6_batch():
+    say("fill candidates full mu7.6 x1000")
+    b = synth.make_batch("mu7.6")
+    p = sbt.make_params(b.module_z)
+    _same(sbt.sbt_debug_reconstruct_fill_candidates(p, sbt.DeviceBatch(b)).to_host(), oracle.reconstruct(b),
+          "fill candidates mu7.6 x1000")

@@ -2,14 +2,26 @@
 (Section 4): the global event cut inside the reconstruction, and
 consolidation against the float64 oracle.
 
+The consolidation oracle is fed the oracle's own tracks, and each test first
+asserts that the GPU's tracks equal them byte for byte, so no input of the
+comparison comes from the HIP path.
+
 Tolerances of the binary32 fit (n hits, unit roundoff u = 2^-24, v one of
-x, y, z): recursive summation of n terms errs by at most (n - 1) u sum|v|,
-so a mean by at most n u max|v| (with the division); the slopes are ratios
-of sums of products of centred values, each centred value carrying the mean's
-error, giving at most a few n u (|t| + sqrt(n) max|v - mean| / sqrt(Szz));
-the test allows twice and four times those.  chi2 is a sum of squared
-residuals that cancel to the 12 um smearing scale: allowed 1 % relative plus
-1e-9 mm^2.  Packed coordinates are copies: exact.
+x, y, z; first-order error propagation, each bound taken twice or four
+times as slack):
+  - a mean: recursive summation of n terms errs by at most (n - 1) u sum|v|,
+    so with the division a mean errs by at most n u max|v|; allowed 2 n u
+    max|v| (call it dm_v).
+  - a slope: a ratio of sums of products of centred values, each centred
+    value carrying the mean's error: a few n u (|t| + sqrt(n) max|v - mean|
+    / sqrt(Szz)); allowed 4 n u (...) (call it dt).
+  - chi2 / (2n - 4): every residual r = v - (vm + t dz), dz = z - zm, is
+    computed from the rounded mean and slope, so it errs by at most
+    e = dm_v + |t| (dm_z + u |dz|) + |dz| dt + u (|t dz| + |vm + t dz| + |r|);
+    a square then errs by 2 |r| e + e^2, and the sum of n squares by the sum
+    of those plus n u chi2; the division adds u chi2 / (2n - 4).  Allowed
+    twice that.
+Packed coordinates are copies: exact.
 """
 
 import sys
@@ -66,21 +78,37 @@ def test_event_cut_matches_oracle(form):
     assert (sizes > c).sum() == 6
 
 
-def _check_states(b, tracks, got):
-    eto, tho, th = tracks
+def _check_states(b, got_tracks, got_states, **params):
+    """The GPU's tracks equal the oracle's; the GPU's consolidation of them
+    equals the float64 consolidation of the oracle's tracks, within the
+    derived bounds."""
+    eto, tho, th = oracle.reconstruct(b, **params)
+    for g, w, what in zip(got_tracks[:3], (eto, tho, th), ("event track offsets", "track hit offsets", "hits")):
+        assert np.array_equal(g, w), f"GPU tracks differ from the oracle's: {what}"
     px, py, pz, st = seq.consolidate(b, eto, tho, th)
-    gx, gy, gz, gs = got
+    gx, gy, gz, gs = got_states
     assert np.array_equal(gx, px) and np.array_equal(gy, py) and np.array_equal(gz, pz)
     assert gs.shape == st.shape
     for t in range(st.shape[0]):
         lo, hi = int(tho[t]), int(tho[t + 1])
         n = hi - lo
         x, y, z = (v[lo:hi].astype(np.float64) for v in (px, py, pz))
-        tol_m = [2 * n * U * np.abs(v).max() for v in (x, y, z)]
+        dm = [2 * n * U * np.abs(v).max() for v in (x, y, z)]
         rz = np.sqrt(((z - z.mean()) ** 2).sum())
-        tol_t = [4 * n * U * (abs(st[t, 3 + j]) + np.sqrt(n) * np.abs(v - v.mean()).max() / rz)
-                 for j, v in enumerate((x, y))]
-        tol = np.array(tol_m + tol_t + [0.01 * st[t, 5] + 1e-9])
+        dt = [4 * n * U * (abs(st[t, 3 + j]) + np.sqrt(n) * np.abs(v - v.mean()).max() / rz)
+              for j, v in enumerate((x, y))]
+        zm = st[t, 2]
+        dz = z - zm
+        c2_err, c2 = 0.0, 0.0
+        for j, v in enumerate((x, y)):
+            vm, tv = st[t, j], st[t, 3 + j]
+            r = v - (vm + tv * dz)
+            e = (dm[j] + abs(tv) * (dm[2] + U * np.abs(dz)) + np.abs(dz) * dt[j]
+                 + U * (np.abs(tv * dz) + np.abs(vm + tv * dz) + np.abs(r)))
+            c2_err += float((2 * np.abs(r) * e + e * e).sum())
+            c2 += float((r * r).sum())
+        tol_c2 = 2 * (c2_err + n * U * c2 + U * c2) / (2 * n - 4)
+        tol = np.array(dm + dt + [tol_c2])
         err = np.abs(gs[t].astype(np.float64) - st[t])
         assert np.all(err <= tol), (t, gs[t], st[t], err, tol)
 
@@ -127,7 +155,7 @@ def test_consolidate_empty_batch_and_trackless_events():
     states = sbt.sbt_consolidate(dev, out)
     torch.cuda.synchronize()
     eto, tho, th, st = out.to_host()
-    _check_states(b, (eto, tho, th), states.to_host(eto[-1], tho[-1]))
+    _check_states(b, (eto, tho, th), states.to_host(eto[-1], tho[-1]), max_event_hits=c)
 
 
 def test_consolidate_tracks_longer_than_the_register_path():
@@ -158,7 +186,5 @@ def test_consolidate_tracks_longer_than_the_register_path():
     states = sbt.sbt_consolidate(dev, out)
     torch.cuda.synchronize()
     eto, tho, th, st = out.to_host()
-    for g, w in zip((eto, tho, th), oracle.reconstruct(b)):
-        assert np.array_equal(g, w)
     assert np.diff(tho).max() > 32
     _check_states(b, (eto, tho, th), states.to_host(eto[-1], tho[-1]))

@@ -174,3 +174,27 @@ def test_replay_driver_counts_match_oracle():
     srv.close()
     assert np.array_equal(nt, counts[picks])
     assert np.all(lat > 0) and wall > 0
+
+
+def test_replay_refused_while_events_are_pending():
+    """The replay driver matches results to arrivals by request id, so it is
+    refused while events submitted earlier are queued, on the device or not
+    yet collected; once they are drained it runs."""
+    say("serving replay refused while busy")
+    pool = synth.make_batch("serve", 6)
+    params = sbt.make_params(pool.module_z)
+    srv = sbt.Server(params, device_budget_bytes=1 << 30, n_slots=2, slot_events=8, slot_hits=1 << 17,
+                     max_wait_us=100)
+    assert srv.submit(123456789, *_event(pool, 0)) == 0
+    with pytest.raises(sbt.SbtError) as ei:
+        srv.replay(pool, np.zeros(3), np.array([0, 1, 2]))
+    assert ei.value.code == sbt.SBT_ERR_NOT_READY
+    got = _drain(srv, 1)
+    assert list(got) == [123456789]
+    assert srv.pending() == (0, 0)
+    with pytest.raises(sbt.SbtError) as ei:
+        srv.replay(pool, np.zeros(2), np.array([0, 6]))      # pick outside the pool
+    assert ei.value.code == sbt.SBT_ERR_INVALID_ARG
+    lat, nt, wall = srv.replay(pool, np.zeros(3), np.array([0, 1, 2]))
+    assert np.array_equal(nt, np.diff(oracle.reconstruct(pool)[0])[[0, 1, 2]])
+    srv.close()
