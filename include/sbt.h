@@ -256,6 +256,29 @@ int sbt_reconstruct_batched(sbt_context *ctx, const sbt_hits *hits, sbt_tracks *
  * (sbt_hits_f16).  Same errors; xyzw must be 8-byte aligned.             */
 int sbt_reconstruct_batched_f16(sbt_context *ctx, const sbt_hits_f16 *hits, sbt_tracks *tracks, void *stream);
 
+/* ---- the batched form without allocation -------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * kernels as sbt_reconstruct_batched, in the launch configuration the
+ * context chooses per call from the batch's size, with their workspace in a
+ * static device array of SBT_STATIC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends (no context, no allocation, no
+ * graph capture of its own; the caller may capture the call).  A batch fits
+ * when sbt_workspace_size(n_events, n_hits) <= SBT_STATIC_SCRATCH_BYTES
+ * (about 680,000 hits for 200 events); a larger one is refused with
+ * SBT_ERR_WORKSPACE before anything is enqueued.  The first call on a device
+ * looks the array's device address up (hipGetSymbolAddress).
+ * Every call on one GPU shares that GPU's array: calls whose work overlaps
+ * on the device (different streams, or different host threads, without
+ * ordering between them) race on it and give undefined results; order them
+ * on one stream or with events.  The kernels initialise all of the array
+ * they read, so the previous call's contents never change a result.
+ * Same outputs as sbt_reconstruct_batched, byte for byte.  Returns SBT_OK,
+ * SBT_ERR_INVALID_ARG, SBT_ERR_WORKSPACE or SBT_ERR_HIP.                   */
+#define SBT_STATIC_SCRATCH_BYTES (64u << 20)
+int sbt_reconstruct_batched_static(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks,
+                                   void *stream);
+
 /* Time the candidate launch configurations on `sample` (reps launches each,
  * after one warm-up) and install the fastest in the context.  `tracks` is
  * scratch output of the sample's size.  Writes the chosen tuning and its mean

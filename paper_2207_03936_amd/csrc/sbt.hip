@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 #include "sbt.h"
@@ -1061,6 +1062,74 @@ int sbt_reconstruct_batched(sbt_context *c, const sbt_hits *hits, sbt_tracks *tr
     int rc;
     if ((rc = check_hits(hits))) return rc;
     return batched(c, hits_args(hits), tracks, stream);
+}
+
+// ---------------------------------------------------------------- no allocation
+// The batched sequence with its workspace in a static device array, for
+// callers that cannot allocate.  Every GPU the library runs on holds its own
+// copy of the array until the process ends.  In host code `scratch` names a
+// host-side stand-in, not the device array: its device address is taken once
+// per device with hipGetSymbolAddress and only that address is passed on.
+// The kernels initialise everything they read (k_prepare resets the work
+// counter; every event clears its flags, claims and links before use), so
+// nothing is cleared on the host.
+}  // extern "C"
+
+static __device__ __align__(256) char scratch[SBT_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices];
+int g_scratch_cus[kMaxDevices];
+
+// The device address of the current device's scratch array and its compute
+// unit count, looked up on the first call on that device.
+int scratch_for_device(char **ptr, int *cus)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return SBT_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255)) return SBT_ERR_HIP;
+        int n = 0;
+        HIP_TRY(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        g_scratch_cus[dev] = n;
+        g_scratch_ptr[dev] = (char *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *cus = g_scratch_cus[dev];
+    return SBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sbt_reconstruct_batched_static(const sbt_params *params, const sbt_hits *hits, sbt_tracks *tracks, void *stream)
+{
+    int rc = sbt_params_validate(params);
+    if (rc) return rc;
+    if ((rc = check_hits(hits)) || (rc = check_tracks(tracks))) return rc;
+    if (carve(hits->n_events, hits->n_hits, nullptr, nullptr) > (size_t)SBT_STATIC_SCRATCH_BYTES)
+        return SBT_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const HitsArgs H = hits_args(hits);
+    const OutArgs O = out_args(tracks);
+    if (H.n_events == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(64), 0, s, O);
+        return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
+    }
+    char *base = nullptr;
+    int cus = 0;
+    if ((rc = scratch_for_device(&base, &cus))) return rc;
+    Work W;
+    carve(H.n_events, H.n_hits, base, &W);
+    return launch_batched(*params, size_tuning(H.n_events, H.n_hits, cus), H, W, O, s, nullptr);
 }
 
 int sbt_reconstruct_batched_f16(sbt_context *c, const sbt_hits_f16 *hits, sbt_tracks *tracks, void *stream)

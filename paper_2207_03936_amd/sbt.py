@@ -129,6 +129,7 @@ PROTOTYPES = {
     "sbt_context_get_tuning": (ctypes.c_int, [_VP, _P(SbtTuning)]),
     "sbt_reconstruct_batched": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP]),
     "sbt_reconstruct_batched_f16": (ctypes.c_int, [_VP, _P(SbtHitsF16), _P(SbtTracks), _VP]),
+    "sbt_reconstruct_batched_static": (ctypes.c_int, [_P(SbtParams), _P(SbtHits), _P(SbtTracks), _VP]),
     "sbt_autotune": (ctypes.c_int, [_VP, _P(SbtHits), _P(SbtTracks), _VP, ctypes.c_int32, _P(SbtTuning),
                                     _P(ctypes.c_float)]),
     "sbt_context_set_profiling": (ctypes.c_int, [_VP, ctypes.c_int32]),
@@ -390,6 +391,20 @@ def sbt_debug_phi_sort(params: SbtParams, batch: DeviceBatch, stream=None, metho
         return phi, ids
     n = batch.n_hits
     return (phi[:n].cpu().numpy().view(np.uint16), ids[:n].cpu().numpy().view(np.uint16))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def sbt_reconstruct_batched_static(params: SbtParams, batch: DeviceBatch, out: Optional[DeviceTracks] = None,
+                                   stream=None) -> DeviceTracks:
+    """The batched form with the library's static scratch as its workspace
+    (no allocation inside the call; asynchronous on torch's current stream)."""
+    out = out or DeviceTracks(batch.n_events, batch.n_hits)
+    _check(lib().sbt_reconstruct_batched_static(ctypes.byref(params), ctypes.byref(batch.hits),
+                                                ctypes.byref(out.tracks), _stream_handle(stream)),
+           "sbt_reconstruct_batched_static")
+    return out
 
 
 # ------------------------------------------------------------------ sequence steps
