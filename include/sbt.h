@@ -229,8 +229,9 @@ typedef struct sbt_context sbt_context;
  * call from the batch's size on the current device: 1,024 lanes per event,
  * one workgroup per compute unit and 1,536-hit LDS slots for a batch of at
  * most one event per compute unit, or at most two of 4,000 hits or more on
- * average; otherwise 512 lanes, two workgroups per compute unit, and 768-hit
- * slots for events of 4,000 hits or more on average, 672-hit slots for
+ * average, or any number of 9,000 hits or more on average; otherwise 512
+ * lanes, two workgroups per compute unit, and 768-hit slots for events of
+ * 4,000 hits or more on average, 672-hit slots for
  * smaller ones, except that more than twelve smaller events per compute unit
  * run 256 lanes, three workgroups per compute unit, 448-hit slots
  * (lds_owner_hits 16,384 throughout).  sbt_context_set_tuning

@@ -489,7 +489,8 @@ def test_full_size_half_precision():
 
 def _expected_choice(n_events, n_hits, cus):
     large = n_hits >= 4000 * n_events
-    if n_events <= cus or (n_events <= 2 * cus and large):
+    huge = n_hits >= 9000 * n_events
+    if n_events <= cus or (n_events <= 2 * cus and large) or huge:
         return (1024, 1, 1536)
     if not large and n_events > 12 * cus:
         return (256, 3, 448)
@@ -497,7 +498,7 @@ def _expected_choice(n_events, n_hits, cus):
 
 
 @pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000),
-                                      ("mu7.6", 3600)])
+                                      ("mu7.6", 3600), ("mu30", 600)])
 def test_configuration_chosen_per_call(config, n):
     """A context created without a launch configuration chooses one per call
     from the batch's size.  Each choice, a smaller batch through the same
