@@ -2,8 +2,9 @@
 called through the C ABI, its outputs equal those of sbt_reconstruct_batched
 on the same inputs and the oracle's, on two calls in a row (the second with a
 smaller batch, so the static scratch still holds the first call's contents),
-and a batch beyond the scratch capacity is refused before any launch.  The
-file name sorts last so that it also runs after every other GPU test."""
+a batch beyond the scratch capacity is refused before any launch, and the
+call can be captured into a caller's graph.  The file name sorts last so
+that it also runs after every other GPU test."""
 
 import ctypes
 import sys
@@ -81,3 +82,36 @@ def test_static_scratch_refuses_oversized_batch():
     import torch
     torch.cuda.synchronize()
     assert int(out.eto[0]) == -7, "a refused call wrote outputs"
+
+
+def test_static_scratch_under_caller_graph_capture():
+    """Captured into a caller's HIP graph (torch.cuda.graph) and replayed
+    three times, with the outputs overwritten eagerly between replays: every
+    replay equals the oracle."""
+    import torch
+    torch.cuda.set_device(0)
+    b = synth.make_batch("mu7.6", 60, first=500)
+    want = oracle.reconstruct(b)
+    p = sbt.make_params(b.module_z)
+    dev = sbt.DeviceBatch(b)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    s = torch.cuda.Stream()
+    say("static scratch: eager call before capture")
+    with torch.cuda.stream(s):
+        assert _static_call(p, dev, out, s.cuda_stream) == sbt.SBT_OK
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("static scratch: capture")
+    with torch.cuda.graph(g, stream=s):
+        rc = _static_call(p, dev, out, torch.cuda.current_stream().cuda_stream)
+    assert rc == sbt.SBT_OK
+    for rep in range(3):
+        say(f"static scratch: replay {rep}")
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.to_host()
+        for x, y in zip(got[:3], want):
+            assert np.array_equal(x, y), f"replay {rep} differs from the oracle"
+        assert not got[3].any()
