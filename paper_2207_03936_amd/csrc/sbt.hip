@@ -32,6 +32,10 @@ using namespace sbt;
 constexpr int kPlainThreads = 256;
 constexpr int kPlainCap = 672;
 constexpr int kPlainOwnCap = 16384;
+// dynamic LDS of the plain compaction kernel: its LDS form (previous-hit
+// links and the key-ordered track list, 2 N + 2 (N / 3 + 1) bytes) fits
+// events of up to about 24,000 hits; larger ones take the memory form
+constexpr int kPlainCompactLds = 64 * 1024;
 
 template <int B>
 __global__ __launch_bounds__(B) void k_phi_sort(sbt_params P, HitsArgs H, Work W, int sortcap)
@@ -118,7 +122,7 @@ __global__ __launch_bounds__(B) void k_weak_filter(sbt_params P, HitsArgs H, Wor
 }
 
 template <int B>
-__global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
+__global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W, int lds_bytes)
 {
     __shared__ int scan[2 * (B / 64)];
     const int e = blockIdx.x;
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W)
         return;
     }
     const int hb = H.eo[e];
-    stage_compact<B>(event_view(W, e, hb, H.eo[e + 1] - hb), scan, 0);
+    stage_compact<B>(event_view(W, e, hb, H.eo[e + 1] - hb), scan, lds_bytes);
 }
 
 // batched form ----------------------------------------------------------------
@@ -486,7 +490,7 @@ int launch_plain_front(const sbt_params &P, const HitsArgs &H, const Work &W, hi
         hipLaunchKernelGGL((k_seed_follow<kPlainThreads, kPlainCap, false>), g, b, lds, s, P, H, W, kPlainOwnCap);
     }
     hipLaunchKernelGGL(k_weak_filter<kPlainThreads>, g, b, 0, s, P, H, W);
-    hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, 0, s, H, W);
+    hipLaunchKernelGGL(k_compact<kPlainThreads>, g, b, kPlainCompactLds, s, H, W, kPlainCompactLds);
     return hipGetLastError() == hipSuccess ? SBT_OK : SBT_ERR_HIP;
 }
 
