@@ -69,10 +69,22 @@ def algorithmic_bytes(batch, eto, tho) -> int:
 
 
 def kernel_source_hash() -> str:
+    """Hash of the source the batched kernels are compiled from: the
+    persistent kernel's translation unit, the device header, the kernel
+    table, the public header (argument layouts) and the event-ordering
+    kernel that runs before it (k_prepare, in sbt.hip).  Host-side code
+    elsewhere in sbt.hip does not enter, so that an unrelated change does not
+    void the committed counter summaries."""
+    csrc = os.path.join(ROOT, "paper_2207_03936_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("sbt_device.h", "sbt.hip", "sbt_persistent.hip", "sbt_kernels.h"):
-        with open(os.path.join(ROOT, "paper_2207_03936_amd", "csrc", f), "rb") as fh:
+    for f in (os.path.join(csrc, "sbt_device.h"), os.path.join(csrc, "sbt_persistent.hip"),
+              os.path.join(csrc, "sbt_kernels.h"), os.path.join(ROOT, "include", "sbt.h")):
+        with open(f, "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "sbt.hip")) as fh:
+        text = fh.read()
+    start = text.index("constexpr int kOrderThreads")
+    h.update(text[start:text.index("\n}\n", start)].encode())
     return h.hexdigest()[:16]
 
 
@@ -514,6 +526,8 @@ def main():
     ap.add_argument("--no-workloads", action="store_true", help="skip the mu1-25 and mu30 legs")
     ap.add_argument("--kernel-only", action="store_true",
                     help="the headline batch alone (graph replays, direct launches, stage timing): for profiles")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="the plain per-event kernels alone on the headline batch: for profiles")
     ap.add_argument("--tpe", type=int, default=0, help="threads per event (0: the library's choice)")
     ap.add_argument("--bpc", type=int, default=0, help="blocks per CU (with --tpe)")
     ap.add_argument("--cap", type=int, default=672, help="LDS slot capacity in hits (with --tpe/--bpc)")
@@ -524,7 +538,7 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): events are independent, so "
               "several GPUs would each run this same per-GPU path on their own events.", file=sys.stderr)
         sys.exit(2)
-    if args.kernel_only:
+    if args.kernel_only or args.plain_only:
         args.no_cpu = args.no_serve = args.no_e2e = args.no_workloads = True
 
     from paper_2207_03936_amd import synth
@@ -571,6 +585,17 @@ def main():
             fn()
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
+
+    if args.plain_only:
+        sec_plain = timed(lambda: sbt.sbt_reconstruct(params, dev, out, ws), args.steps, args.warmup)
+        got_plain = out.to_host()
+        ctx.close()
+        print(json.dumps({"metric": "events/s of the plain per-event kernels", "value": round(E / sec_plain, 1),
+                          "unit": "events/s", "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": round(sec_plain * 1e3, 4), "form": "plain",
+                          "config": {"workload": WORKLOADS[args.workload].format(E=E), "n_events": E, "n_hits": H},
+                          "n_tracks": int(got_plain[0][-1])}), flush=True)
+        return
 
     # batched: the persistent kernel and its tail replayed as a captured graph
     graph_call = lambda: ctx.reconstruct(dev, out, gstream)

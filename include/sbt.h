@@ -208,8 +208,8 @@ int sbt_validate_offsets_host(int32_t n_modules, int32_t n_events, int32_t n_hit
  * Bytes of device workspace sbt_reconstruct needs for a batch of this size. */
 int sbt_workspace_size(int32_t n_events, int32_t n_hits, size_t *bytes);
 
-/* Reconstruct a batch with the plain per-event kernels: one workgroup per
- * event and one launch per stage (phi sort, seeding and following, tracklet
+/* Reconstruct a batch with the plain per-event kernels: one workgroup of 512
+ * lanes per event and one launch per stage (phi sort, seeding and following, tracklet
  * filter, per-event compaction, scan over events, CSR write), all enqueued on
  * `stream`.  `workspace` is caller-owned device memory of at least
  * sbt_workspace_size() bytes, 256-byte aligned; it must not be used by

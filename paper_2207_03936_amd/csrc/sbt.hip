@@ -29,7 +29,10 @@ using namespace sbt;
 
 // plain form ----------------------------------------------------------------
 
-constexpr int kPlainThreads = 256;
+// one workgroup of 512 lanes per event: on the mu=7.6 x 1,000, mu in
+// U{1..25} x 2,000 and mu=30 x 400 batches 512 lanes beat 256 (1.30x, 1.34x,
+// 1.49x) and 1,024 (except on the densest events)
+constexpr int kPlainThreads = 512;
 constexpr int kPlainCap = 672;
 constexpr int kPlainOwnCap = 16384;
 // dynamic LDS of the plain compaction kernel: its LDS form (previous-hit
