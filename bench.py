@@ -100,13 +100,18 @@ def _summary(name, per_launch_hits: int, tuning: dict):
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_source_hash() or d.get("n_hits") != per_launch_hits:
         return None
-    want = {k: int(tuning[k]) for k in TUNING_KEYS}
-    if {k: d.get("tuning", {}).get(k) for k in TUNING_KEYS} != want:
+    if _tuning_key(d.get("tuning", {})) != _tuning_key(tuning):
         return None
     return d
 
 
-TUNING_KEYS = ("threads_per_event", "blocks_per_cu", "lds_window_hits")
+TUNING_KEYS = ("threads_per_event", "blocks_per_cu", "lds_window_hits", "events_per_block")
+
+
+def _tuning_key(t: dict):
+    """The launch configuration a summary is valid for (events per workgroup
+    reads as 1 where a configuration does not name it)."""
+    return tuple(int(t.get(k, 1)) if k == "events_per_block" else t.get(k) for k in TUNING_KEYS)
 
 
 def measured_traffic(per_launch_hits: int, tuning: dict):

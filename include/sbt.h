@@ -184,12 +184,19 @@ typedef struct sbt_tracks {
  * lds_owner_hits      events with at most this many hits keep their hit
  *                     flags (one bit per hit) in LDS, larger ones in
  *                     memory (0..65536).
- * The two LDS capacities together take at most 159 KiB per workgroup.    */
+ * events_per_block    events one workgroup runs side by side (0 or 1: one;
+ *                     up to 16, only with threads_per_event = 64).  Each
+ *                     64-lane event is one wave with its own LDS region and
+ *                     takes its next event from the queue on its own, so the
+ *                     waves of a workgroup never wait for one another.
+ * The LDS of a workgroup (both capacities, times events_per_block for
+ * 64-lane events) is at most 159 KiB.                                      */
 typedef struct sbt_tuning {
     int32_t threads_per_event;
     int32_t blocks_per_cu;
     int32_t lds_window_hits;
     int32_t lds_owner_hits;
+    int32_t events_per_block;
 } sbt_tuning;
 
 /* Message for a return code (static storage). */

@@ -514,7 +514,20 @@ int effective_cap(int requested)
     return c;
 }
 
-uint32_t tuning_lds(const sbt_tuning &T) { return lds_bytes(effective_cap(T.lds_window_hits), T.lds_owner_hits); }
+// events a workgroup runs side by side (0 reads as 1)
+int events_per_block(const sbt_tuning &T) { return T.events_per_block > 1 ? T.events_per_block : 1; }
+
+// lanes of a persistent workgroup
+int block_lanes(const sbt_tuning &T) { return T.threads_per_event * events_per_block(T); }
+
+// dynamic LDS of a persistent workgroup: 64-lane events carry their Shared
+// block in it, one region per event; wider ones keep it in static LDS
+uint32_t tuning_lds(const sbt_tuning &T)
+{
+    const int cap = effective_cap(T.lds_window_hits);
+    if (T.threads_per_event == 64) return (uint32_t)events_per_block(T) * event_region_bytes<64>(cap, T.lds_owner_hits);
+    return lds_bytes(cap, T.lds_owner_hits);
+}
 
 const void *persistent_kernel(int tpe, int cap)
 {
@@ -551,7 +564,7 @@ int persistent_occupancy(const sbt_tuning &T, int *occ)
     if (!fn) return SBT_ERR_INVALID_ARG;
     const size_t lds = tuning_lds(T);
     if (int rc = allow_lds(fn, lds)) return rc;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, fn, T.threads_per_event, lds));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, fn, block_lanes(T), lds));
     return SBT_OK;
 }
 
@@ -562,7 +575,8 @@ int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
     if (rc) return rc;
     if ((rc = persistent_occupancy(T, &occ))) return rc;
     int bpc = std::max(1, std::min(T.blocks_per_cu, std::max(occ, 1)));
-    *grid = std::max(1, std::min(cus * bpc, std::max(n_events, 1)));
+    const int epb = events_per_block(T);
+    *grid = std::max(1, std::min(cus * bpc, (std::max(n_events, 1) + epb - 1) / epb));
     return SBT_OK;
 }
 
@@ -581,8 +595,8 @@ int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &
     Work Wc = W;
     void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap};
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
-    HIP_TRY(hipLaunchKernel(persistent_kernel(T.threads_per_event, cap), dim3(grid), dim3(T.threads_per_event), args,
-                            lds, s));
+    HIP_TRY(hipLaunchKernel(persistent_kernel(T.threads_per_event, cap), dim3(grid), dim3(block_lanes(T)), args, lds,
+                            s));
     return SBT_OK;
 }
 
@@ -849,6 +863,8 @@ int valid_tuning(const sbt_tuning &t)
     if (t.blocks_per_cu < 1 || t.blocks_per_cu > 16) return SBT_ERR_INVALID_ARG;
     if (t.lds_window_hits < 0 || t.lds_window_hits > 2048) return SBT_ERR_INVALID_ARG;
     if (t.lds_owner_hits < 0 || t.lds_owner_hits > 65536) return SBT_ERR_INVALID_ARG;
+    if (t.events_per_block < 0 || t.events_per_block > kMaxEventsPerBlock) return SBT_ERR_INVALID_ARG;
+    if (events_per_block(t) > 1 && t.threads_per_event != 64) return SBT_ERR_INVALID_ARG;
     if (tuning_lds(t) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
     return SBT_OK;
 }
@@ -860,6 +876,7 @@ sbt_tuning default_tuning()
     t.blocks_per_cu = 2;
     t.lds_window_hits = 672;
     t.lds_owner_hits = 16384;
+    t.events_per_block = 1;
     return t;
 }
 
@@ -1168,42 +1185,47 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
         (void)hipEventDestroy(t0);
         return SBT_ERR_HIP;
     }
-    // candidates: lanes per event x LDS slot capacity, each at the largest
-    // number of resident workgroups per CU and one less
-    const int tpes[] = {128, 256, 512, 1024};
-    const int caps[] = {256, 448, 672, 768, 1024, 1536};
+    // candidates: lanes per event x LDS slot capacity (x events per
+    // workgroup for 64-lane events), each at the largest number of resident
+    // workgroups per CU and one less
+    struct Cand {
+        int tpe, cap, epb;
+    };
+    std::vector<Cand> cands;
+    for (int tpe : {128, 256, 512, 1024})
+        for (int cap : {256, 448, 672, 768, 1024, 1536}) cands.push_back({tpe, cap, 1});
+    for (int epb : {2, 4, 8})
+        for (int cap : {256, 448}) cands.push_back({64, cap, epb});
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;
     rc = SBT_OK;
-    for (int tpe : tpes) {
-        for (int cap : caps) {
-            sbt_tuning t = c->tuning;
-            t.threads_per_event = tpe;
-            t.lds_window_hits = cap;
-            t.lds_owner_hits = 16384;
-            if (valid_tuning(t) != SBT_OK) continue;
-            int occ = 0;
-            if ((rc = persistent_occupancy(t, &occ))) break;
-            if (occ < 1) continue;
-            for (int bpc = occ; bpc >= 1 && bpc >= occ - 1; --bpc) {
-                t.blocks_per_cu = bpc;
-                if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
-                if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
-                for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);
-                if (rc) break;
-                float ms = 0.0f;
-                if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
-                    hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
-                    rc = SBT_ERR_HIP;
-                    break;
-                }
-                ms /= (float)reps;
-                if (win_ms < 0.0f || ms < win_ms) {
-                    win_ms = ms;
-                    win = t;
-                }
-            }
+    for (const Cand &cd : cands) {
+        sbt_tuning t = c->tuning;
+        t.threads_per_event = cd.tpe;
+        t.lds_window_hits = cd.cap;
+        t.lds_owner_hits = cd.tpe == 64 ? 4096 : 16384;
+        t.events_per_block = cd.epb;
+        if (valid_tuning(t) != SBT_OK) continue;
+        int occ = 0;
+        if ((rc = persistent_occupancy(t, &occ))) break;
+        if (occ < 1) continue;
+        for (int bpc = occ; bpc >= 1 && bpc >= occ - 1; --bpc) {
+            t.blocks_per_cu = bpc;
+            if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
+            if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
+            for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);
             if (rc) break;
+            float ms = 0.0f;
+            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                hipEventElapsedTime(&ms, t0, t1) != hipSuccess) {
+                rc = SBT_ERR_HIP;
+                break;
+            }
+            ms /= (float)reps;
+            if (win_ms < 0.0f || ms < win_ms) {
+                win_ms = ms;
+                win = t;
+            }
         }
         if (rc) break;
     }

@@ -191,6 +191,44 @@ __device__ __forceinline__ void lds_barrier()
 // moved to a scalar register.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Lane index among the lanes that run one event.  An event of 64 lanes is
+// one wave, and a workgroup may hold several of them, one event per wave;
+// wider events have their workgroup to themselves.
+template <int B>
+__device__ __forceinline__ int tid()
+{
+    return B == 64 ? (int)(threadIdx.x & 63u) : (int)threadIdx.x;
+}
+
+// Barrier over the lanes of one event.  The lanes of a 64-lane event are one
+// wave and run in lockstep, so only its memory operations have to complete
+// (the fences); the workgroup's other waves run other events and are not
+// waited for.
+template <int B>
+__device__ __forceinline__ void ev_sync()
+{
+    if (B == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+// The same for phases that exchange LDS data only (see lds_barrier).
+template <int B>
+__device__ __forceinline__ void ev_lds_sync()
+{
+    if (B == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        lds_barrier();
+    }
+}
+
 // The value, hidden from the optimiser at this point.  Stages re-read the
 // scalar parameters and the workspace base through this at the start of
 // every module step, so values derived from them are recomputed per step
@@ -324,8 +362,8 @@ template <int B>
 __device__ __forceinline__ int waves_before(int wave_total, int *s_w, int *total)
 {
     constexpr int NW = B / 64;
-    const int w = uni((int)(threadIdx.x >> 6));
-    if ((threadIdx.x & 63) == 0) s_w[w] = wave_total;
+    const int w = uni((int)(tid<B>() >> 6));
+    if ((tid<B>() & 63) == 0) s_w[w] = wave_total;
     lds_barrier();
     int before = 0, all = 0;
 #pragma unroll
@@ -372,7 +410,7 @@ template <int B>
 __device__ void block_scan_inplace(int *a, int n, int *s_w)
 {
     const int chunk = (n + B - 1) / B;
-    const int beg = threadIdx.x * chunk;
+    const int beg = tid<B>() * chunk;
     const int end = beg + chunk < n ? beg + chunk : n;
     int sum = 0;
     for (int i = beg; i < end; ++i) sum += a[i];
@@ -453,27 +491,30 @@ __host__ __device__ inline int sort_shift(int M)
 
 template <int CAP>
 struct Lay {
-    static __device__ __forceinline__ Hit16 *ring(int s) { return reinterpret_cast<Hit16 *>(g_lds) + s * CAP; }
-    static __device__ __forceinline__ uint16_t *tab(int s)
+    static __device__ __forceinline__ Hit16 *ring(uint32_t lo, int s)
     {
-        return reinterpret_cast<uint16_t *>(g_lds + lay_tab(CAP)) + s * kTab;
+        return reinterpret_cast<Hit16 *>(g_lds + lo) + s * CAP;
     }
-    static __device__ __forceinline__ uint16_t *freel() { return reinterpret_cast<uint16_t *>(g_lds + lay_freel(CAP)); }
-    static __device__ __forceinline__ uint16_t *freem() { return reinterpret_cast<uint16_t *>(g_lds + lay_freem(CAP)); }
-    static __device__ __forceinline__ uint16_t *frank() { return reinterpret_cast<uint16_t *>(g_lds + lay_frank(CAP)); }
-    static __device__ __forceinline__ uint16_t *al(int i)
+    static __device__ __forceinline__ uint16_t *tab(uint32_t lo, int s)
     {
-        return reinterpret_cast<uint16_t *>(g_lds + (i ? lay_al1(CAP) : lay_al0(CAP)));
+        return reinterpret_cast<uint16_t *>(g_lds + lo + lay_tab(CAP)) + s * kTab;
     }
-    static __device__ __forceinline__ uint4 *res() { return reinterpret_cast<uint4 *>(g_lds + lay_res(CAP)); }
-    static __device__ __forceinline__ uint32_t *own() { return reinterpret_cast<uint32_t *>(g_lds + lay_own(CAP)); }
-    static __device__ __forceinline__ unsigned long long *cfree()
+    static __device__ __forceinline__ uint16_t *freel(uint32_t lo) { return reinterpret_cast<uint16_t *>(g_lds + lo + lay_freel(CAP)); }
+    static __device__ __forceinline__ uint16_t *freem(uint32_t lo) { return reinterpret_cast<uint16_t *>(g_lds + lo + lay_freem(CAP)); }
+    static __device__ __forceinline__ uint16_t *frank(uint32_t lo) { return reinterpret_cast<uint16_t *>(g_lds + lo + lay_frank(CAP)); }
+    static __device__ __forceinline__ uint16_t *al(uint32_t lo, int i)
     {
-        return reinterpret_cast<unsigned long long *>(g_lds + lay_cfree(CAP));
+        return reinterpret_cast<uint16_t *>(g_lds + lo + (i ? lay_al1(CAP) : lay_al0(CAP)));
     }
-    static __device__ __forceinline__ unsigned long long *lclaim()
+    static __device__ __forceinline__ uint4 *res(uint32_t lo) { return reinterpret_cast<uint4 *>(g_lds + lo + lay_res(CAP)); }
+    static __device__ __forceinline__ uint32_t *own(uint32_t lo) { return reinterpret_cast<uint32_t *>(g_lds + lo + lay_own(CAP)); }
+    static __device__ __forceinline__ unsigned long long *cfree(uint32_t lo)
     {
-        return reinterpret_cast<unsigned long long *>(g_lds + lay_lclaim(CAP));
+        return reinterpret_cast<unsigned long long *>(g_lds + lo + lay_cfree(CAP));
+    }
+    static __device__ __forceinline__ unsigned long long *lclaim(uint32_t lo)
+    {
+        return reinterpret_cast<unsigned long long *>(g_lds + lo + lay_lclaim(CAP));
     }
 };
 
@@ -491,12 +532,27 @@ struct Shared {
     uint8_t mtab[(SBT_MAX_EVENT_HITS + 64) / 64];   // module of every 64th hit (sort)
 };
 
+// Events of 64 lanes run one per wave, up to this many in a workgroup; each
+// takes a region of the dynamic LDS: its Shared block, then its layout.
+constexpr int kMaxEventsPerBlock = 16;
+template <int B>
+__host__ __device__ constexpr uint32_t shared_block_bytes()
+{
+    return a16((uint32_t)sizeof(Shared<B>));
+}
+template <int B>
+__host__ __device__ inline uint32_t event_region_bytes(int cap, int own_cap)
+{
+    return shared_block_bytes<B>() + lds_bytes(cap, own_cap);
+}
+
 // per-event views of the workspace: pointers are derived on use from the
 // base, the capacity H and the event's hit offset hb
 struct Ev {
     char *base;
     uint32_t H, E;
     int e, hb, N;
+    uint32_t lo;   // byte offset of the event's region in the workgroup's dynamic LDS
     template <class T>
     __device__ __forceinline__ T *arr(uint32_t off, uint32_t elem) const
     {
@@ -524,7 +580,7 @@ struct Ev {
     }
 };
 
-__device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N)
+__device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N, uint32_t lo = 0)
 {
     Ev v;
     v.base = opq_global(W.base);
@@ -533,6 +589,7 @@ __device__ __forceinline__ Ev event_view(const Work &W, int e, int hb, int N)
     v.e = e;
     v.hb = hb;
     v.N = N;
+    v.lo = lo;
     return v;
 }
 
@@ -553,18 +610,18 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
 {
     const int M = P.n_modules;
     int lo = H.eo[e], hi = H.eo[e + 1];
-    if (threadIdx.x == 0) {
+    if (tid<B>() == 0) {
         S.status = 0;
         S.maxmod = 0;
     }
-    __syncthreads();
+    ev_sync<B>();
     unsigned st = 0;
     if (lo < 0 || hi > H.n_hits || hi < lo) st = SBT_EV_BAD_OFFSETS;
     else if (hi - lo > SBT_MAX_EVENT_HITS) st = SBT_EV_TOO_LARGE;
     else if (P.max_event_hits > 0 && hi - lo > P.max_event_hits) st = SBT_EV_CUT;
     if (st == 0) {
         const long long base = (long long)e * M;
-        for (int k = threadIdx.x; k <= M; k += B) {
+        for (int k = tid<B>(); k <= M; k += B) {
             int v = H.mo[base + k];
             S.mo[k] = v - lo;
             bool bad = (k == 0 && v != lo) || (k == M && v != hi) || v < lo || v > hi;
@@ -572,10 +629,10 @@ __device__ int load_event(const sbt_params &P, const HitsArgs &H, int e, Shared<
             if (bad) atomicOr(&S.status, (int)SBT_EV_BAD_OFFSETS);
             if (k < M) atomicMax(&S.maxmod, H.mo[base + k + 1] - v);
         }
-    } else if (threadIdx.x == 0) {
+    } else if (tid<B>() == 0) {
         S.status = (int)st;
     }
-    __syncthreads();
+    ev_sync<B>();
     *hb_out = uni(lo);
     *n_out = uni(hi - lo);
     return uni(S.status);
@@ -653,19 +710,19 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
     const int shift = sort_shift(M);
     const int bpm = 1 << (16 - shift);
     const int nb = M * bpm;
-    int *hist = reinterpret_cast<int *>(g_lds);
+    int *hist = reinterpret_cast<int *>(g_lds + v.lo);
     int *fill = hist + kSortBins + 1;
-    uint32_t *lkeys = reinterpret_cast<uint32_t *>(g_lds + lds_sort_head());
+    uint32_t *lkeys = reinterpret_cast<uint32_t *>(g_lds + v.lo + lds_sort_head());
     const int form = 2 * N <= sortcap ? 0 : (N <= sortcap ? 1 : 2);
-    for (int i = threadIdx.x; i <= nb; i += B) hist[i] = 0;
-    for (int i = threadIdx.x; i < nb; i += B) fill[i] = 0;
-    for (int c = threadIdx.x; c < (N + 63) / 64; c += B) S.mtab[c] = (uint8_t)module_of(S.mo, M, c * 64);
-    __syncthreads();
+    for (int i = tid<B>(); i <= nb; i += B) hist[i] = 0;
+    for (int i = tid<B>(); i < nb; i += B) fill[i] = 0;
+    for (int c = tid<B>(); c < (N + 63) / 64; c += B) S.mtab[c] = (uint8_t)module_of(S.mo, M, c * 64);
+    ev_sync<B>();
     const HitSrc src = hit_src(H, v.hb);
     // memory form: bins in the claim words (not yet in use)
     uint32_t *bins_m = reinterpret_cast<uint32_t *>(v.claim());
     // the coordinates of a lane's next kSortChunk hits are loaded together
-    for (int i0 = threadIdx.x; i0 < N; i0 += kSortChunk * B) {
+    for (int i0 = tid<B>(); i0 < N; i0 += kSortChunk * B) {
         float px[kSortChunk], py[kSortChunk];
 #pragma unroll
         for (int j = 0; j < kSortChunk; ++j)
@@ -682,18 +739,18 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
             atomicAdd(&hist[bin], 1);
         }
     }
-    __syncthreads();
+    ev_sync<B>();
     block_scan_inplace<B>(hist, nb + 1, S.scan);
-    __syncthreads();
+    ev_sync<B>();
     // separate LDS and memory branches keep each access in its address space
     if (form == 0) {
-        for (int i = threadIdx.x; i < N; i += B) {
+        for (int i = tid<B>(); i < N; i += B) {
             const uint32_t tb = lkeys[N + i];
             const int bin = (int)(tb >> 16);
             lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = (tb << 16) | (uint32_t)i;
         }
     } else if (form == 1) {
-        for (int i = threadIdx.x; i < N; i += B) {
+        for (int i = tid<B>(); i < N; i += B) {
             float px, py;
             src.xy(i, px, py);
             const uint16_t qi = phi16(px, py);
@@ -701,14 +758,14 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
             lkeys[hist[bin] + atomicAdd(&fill[bin], 1)] = ((uint32_t)qi << 16) | (uint32_t)i;
         }
     } else {
-        for (int i = threadIdx.x; i < N; i += B) {
+        for (int i = tid<B>(); i < N; i += B) {
             const uint32_t tb = at(bins_m, i);
             const int bin = (int)(tb >> 16);
             at(v.keys(), hist[bin] + atomicAdd(&fill[bin], 1)) = (tb << 16) | (uint32_t)i;
         }
     }
-    __syncthreads();
-    for (int s = threadIdx.x; s < N; s += B) {
+    ev_sync<B>();
+    for (int s = tid<B>(); s < N; s += B) {
         uint32_t key;
         int i, rank;
         if (form != 2) {
@@ -732,7 +789,7 @@ __device__ void stage_sort(const sbt_params &PP, const HitsArgs &H, const Ev &v0
         h.qid = (key >> 16) | (key << 16);
         at(v.hs(), rank) = h;
     }
-    __syncthreads();
+    ev_sync<B>();
 }
 
 // ---------------------------------------------------------------- module windows
@@ -777,8 +834,8 @@ __device__ __forceinline__ Win window(const Prm &P, const Shared<B> &S, const Ev
     if (kLds) {
         const int s = u % kSlots;
         w.n = uni(S.slot_n[s]);
-        w.h = Lay<CAP>::ring(s);
-        w.tab = Lay<CAP>::tab(s);
+        w.h = Lay<CAP>::ring(v.lo, s);
+        w.tab = Lay<CAP>::tab(v.lo, s);
     } else {
         const int k = kmod(P, u);
         const int g0 = uni(S.mo[k]);
@@ -804,14 +861,14 @@ __device__ __forceinline__ void tab_fill(uint16_t *tab, int i, uint16_t q, uint1
 template <int B, int CAP>
 __device__ __forceinline__ void ring_fill(const Prm &P, const Ev &v, int u, Shared<B> &S, int l0)
 {
-    const int lane = (int)threadIdx.x - l0, nl = B - l0;
+    const int lane = (int)tid<B>() - l0, nl = B - l0;
     if (lane < 0) return;
     const int k = kmod(P, u);
     const int g = uni(S.mo[k]), n = uni(S.mo[k + 1]) - g;
     const int s = u % kSlots;
     if (lane == 0) S.slot_n[s] = n;
-    Hit16 *ring = Lay<CAP>::ring(s);
-    uint16_t *tab = Lay<CAP>::tab(s);
+    Hit16 *ring = Lay<CAP>::ring(v.lo, s);
+    uint16_t *tab = Lay<CAP>::tab(v.lo, s);
     const Hit16 *src = v.hs() + g;
     // n == 0: every entry is 0
     int hi_first = kTab, hi_last = kTab;
@@ -1046,7 +1103,7 @@ __device__ __forceinline__ void put_result(const Ev &v, int a, int r, uint32_t p
         w.y = __float_as_uint(bsc);
         w.z = (uint32_t)R.key | ((uint32_t)(R.len == 3 ? R.h0 : kNone) << 16);
         w.w = (uint32_t)R.h1 | ((uint32_t)R.h2 << 16);
-        Lay<CAP>::res()[a] = w;
+        Lay<CAP>::res(v.lo)[a] = w;
     } else {
         RecAux &x = at(v.aux(), r);
         x.best = pb;
@@ -1090,9 +1147,9 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
     // unflagged positions of the doublet module and of the middle module, ascending
     uint16_t *F, *FR, *FM;
     if (kLds) {
-        F = Lay<CAP>::freel();
-        FR = Lay<CAP>::frank();
-        FM = Lay<CAP>::freem();
+        F = Lay<CAP>::freel(v.lo);
+        FR = Lay<CAP>::frank(v.lo);
+        FM = Lay<CAP>::freem(v.lo);
     } else {
         const int ga = uni(S.mo[kmod(P, t - 2)]), gb = uni(S.mo[kmod(P, t - 1)]);
         F = v.list(kListFreeL) + ga;
@@ -1102,18 +1159,18 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
     int nf = 0, nfm = 0;
     int nmax = na > nbm ? na : nbm;
     if (kLds && wc.n > nmax) nmax = wc.n;
-    unsigned long long *cfree = kLds ? Lay<CAP>::cfree() : nullptr;
-    unsigned long long *lclaim = kLds ? Lay<CAP>::lclaim() : nullptr;
+    unsigned long long *cfree = kLds ? Lay<CAP>::cfree(v.lo) : nullptr;
+    unsigned long long *lclaim = kLds ? Lay<CAP>::lclaim(v.lo) : nullptr;
     if (kLds && follow_next)
-        for (int p = threadIdx.x; p < wn.n; p += B) lclaim[p] = kNoClaim;
+        for (int p = tid<B>(); p < wn.n; p += B) lclaim[p] = kNoClaim;
     int phase = 0;
     for (int base = 0; base < nmax; base += B, ++phase) {
-        const int p = base + (int)threadIdx.x;
+        const int p = base + (int)tid<B>();
         const bool fa = p < na && is_free(own, win_id(wa, p));
         const bool fb = p < nbm && is_free(own, win_id(wb, p));
         if (kLds) {
             const unsigned long long m = __ballot(p < wc.n && is_free(own, win_id(wc, p)));
-            if ((threadIdx.x & 63) == 0 && p < wc.n) at(cfree, (uint32_t)p >> 6) = m;
+            if ((tid<B>() & 63) == 0 && p < wc.n) at(cfree, (uint32_t)p >> 6) = m;
         }
         int total;
         const int idx = block_count2<B>(fa, fb, S.scan, phase, &total);
@@ -1124,8 +1181,8 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
         nfm += total >> 16;
     }
     // the lists are in LDS in the LDS instantiation, in memory otherwise
-    if (kLds) lds_barrier();
-    else __syncthreads();
+    if (kLds) ev_lds_sync<B>();
+    else ev_sync<B>();
     const int hd = na >> 1, hu = na - hd - 1;   // offsets visited: [-hd, hu]
     const int G = (K == 1 || K == 2 || K == 4 || K == 8 || K == 16) ? K : 1;
     const int per_lane = G == 1 ? K : 1;
@@ -1135,8 +1192,8 @@ __device__ void stage_seed_follow(const sbt_params &PP, const Ev &v0, int t, Sha
     const int total = seed_pad + follow_items;
 
     for (int base = 0; base < total; base += B) {
-        const int g = base + (int)threadIdx.x;
-        const int g_wave = uni(base + ((int)threadIdx.x & ~63));
+        const int g = base + (int)tid<B>();
+        const int g_wave = uni(base + ((int)tid<B>() & ~63));
         if (g_wave >= seed_pad) {
             const int a = g - seed_pad;
             if (a < follow_items) {
@@ -1243,7 +1300,7 @@ __device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, 
     const unsigned long long *__restrict__ claim = v.claim();
     uint16_t *fin = v.list(kListFin);
     for (int base = 0; base < n_act; base += B) {
-        const int a = base + (int)threadIdx.x;
+        const int a = base + (int)tid<B>();
         bool done = false, keep = false;
         int r = 0;
         if (a < n_act) {
@@ -1251,7 +1308,7 @@ __device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, 
             uint32_t pb, k0 = 0, k12 = 0;
             float bsc;
             if (kLds) {
-                const uint4 w = Lay<CAP>::res()[a];
+                const uint4 w = Lay<CAP>::res(v.lo)[a];
                 pb = w.x;
                 bsc = __uint_as_float(w.y);
                 k0 = w.z;
@@ -1271,7 +1328,7 @@ __device__ void stage_follow_resolve(const sbt_params &PP, const Ev &v0, int t, 
                 const uint16_t best = (uint16_t)(pb & 0xFFFF);
                 const unsigned long long kap = claim_key(bsc, (uint16_t)(k0 & 0xFFFFu), t);
                 const uint16_t h0 = (uint16_t)(k0 >> 16);
-                win = kLds ? Lay<CAP>::lclaim()[pb >> 16] == kap : at(claim, best) == kap;
+                win = kLds ? Lay<CAP>::lclaim(v.lo)[pb >> 16] == kap : at(claim, best) == kap;
                 if (h0 != kNone)
                     win = win && at(claim, h0) == kap && at(claim, (uint16_t)(k12 & 0xFFFFu)) == kap &&
                           at(claim, (uint16_t)(k12 >> 16)) == kap;
@@ -1327,22 +1384,22 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
 {
     const Prm P = fresh(PP);
     const int M = P.M, N = v.N;
-    uint32_t *own = kLds ? Lay<CAP>::own() : v.own();
+    uint32_t *own = kLds ? Lay<CAP>::own(v.lo) : v.own();
     const int nw = (N + 31) >> 5;
-    for (int i = threadIdx.x; i < nw; i += B) at(own, i) = 0u;
-    for (int i = threadIdx.x; i < N; i += B) {
+    for (int i = tid<B>(); i < nw; i += B) at(own, i) = 0u;
+    for (int i = tid<B>(); i < N; i += B) {
         at(v.claim(), i) = kNoClaim;
         at(v.link(), 2u * i + 1u) = kNone;
     }
-    if (threadIdx.x == 0) {
+    if (tid<B>() == 0) {
         S.cnt[0] = 0; S.cnt[1] = 0; S.cnt[2] = 0; S.cnt[3] = 0;
         S.ovf = 0;
     }
     if (kLds)
         for (int u = 0; u < 4 && u < M; ++u) ring_fill<B, CAP>(P, v, u, S, 0);
-    __syncthreads();
-    uint16_t *l0 = kLds ? Lay<CAP>::al(0) : v.list(kListAct0);
-    uint16_t *l1 = kLds ? Lay<CAP>::al(1) : v.list(kListAct1);
+    ev_sync<B>();
+    uint16_t *l0 = kLds ? Lay<CAP>::al(v.lo, 0) : v.list(kListAct0);
+    uint16_t *l1 = kLds ? Lay<CAP>::al(v.lo, 1) : v.list(kListAct1);
     // the last traversal index whose seeding can make a seed: its modules
     // t-2, t-1 and t all hold hits (2 when no index can)
     int last_seed = 2;
@@ -1356,7 +1413,7 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
     last_seed = uni(last_seed);
     int par = 0;
     stage_seed_follow<B, kLds, CAP, kCand>(PP, v, 2, S, own, l0, &S.cnt[1], 0, M > 3);
-    __syncthreads();
+    ev_sync<B>();
     if (kLds && uni(S.ovf)) return false;
     for (int t = 3; t < M; ++t) {
         // act (n_act tracks) holds every forming track with its search into
@@ -1378,12 +1435,12 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
             if (l0 > B - 64) l0 = B - 64;
             ring_fill<B, CAP>(fresh(PP), fresh(v), t + 1, S, l0);
         }
-        __syncthreads();
+        ev_sync<B>();
         const int n_keep = uni(S.cnt[1 + (par ^ 1)]);
-        if (threadIdx.x == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
+        if (tid<B>() == 0) S.cnt[1 + par] = 0;   // act becomes the next step's nxt
         if (!(kLds && uni(S.ovf)))
             stage_seed_follow<B, kLds, CAP, kCand>(PP, v, t, S, own, nxt, &S.cnt[1 + (par ^ 1)], n_keep, more);
-        __syncthreads();
+        ev_sync<B>();
         if (kLds && uni(S.ovf)) return false;
         par ^= 1;
     }
@@ -1391,12 +1448,12 @@ __device__ bool stage_track_impl(const sbt_params &PP, const Ev &v, Shared<B> &S
     const int nf = uni(S.cnt[3]);
     const uint16_t *act = par ? l1 : l0;
     uint16_t *fin = v.list(kListFin);
-    for (int a = threadIdx.x; a < n_act; a += B) at(fin, nf + a) = at(act, a);
+    for (int a = tid<B>(); a < n_act; a += B) at(fin, nf + a) = at(act, a);
     if (kLds && writeback)
-        for (int i = threadIdx.x; i < nw; i += B) at(v.own(), i) = at(own, i);
-    __syncthreads();
-    if (threadIdx.x == 0) S.cnt[3] = nf + n_act;
-    __syncthreads();
+        for (int i = tid<B>(); i < nw; i += B) at(v.own(), i) = at(own, i);
+    ev_sync<B>();
+    if (tid<B>() == 0) S.cnt[3] = nf + n_act;
+    ev_sync<B>();
     return true;
 }
 
@@ -1433,7 +1490,7 @@ __device__ void stage_fill_candidates(const sbt_params &PP, const Ev &v0, const 
         wa.h = v.hs() + S.mo[ka];
         wa.n = S.mo[ka + 1] - S.mo[ka];
         wa.tab = nullptr;
-        for (int i = threadIdx.x; i < n; i += B) {
+        for (int i = tid<B>(); i < n; i += B) {
             int s0 = wa.n > 0 ? win_lower_bound<false>(wa, q_of(at(v.hs(), (uint32_t)(g0 + i)))) : 0;
             if (s0 == wa.n) s0 = 0;
             at(v.keys(), (uint32_t)(g0 + i)) = (uint32_t)s0;
@@ -1452,7 +1509,7 @@ __device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, cons
     const float X = fresh(PP).X;
     unsigned long long *__restrict__ claim = v.claim();
     const uint16_t *fin = v.list(kListFin);
-    for (int a = threadIdx.x; a < n_fin; a += B) {
+    for (int a = tid<B>(); a < n_fin; a += B) {
         const int r = at(fin, a);
         const Rec R = at(v.rec(), r);
         uint32_t fl = 0;
@@ -1470,8 +1527,8 @@ __device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, cons
         }
         at(v.aux(), r).flag = fl;
     }
-    __syncthreads();
-    for (int a = threadIdx.x; a < n_fin; a += B) {
+    ev_sync<B>();
+    for (int a = tid<B>(); a < n_fin; a += B) {
         const int r = at(fin, a);
         const RecAux x = at(v.aux(), r);
         uint32_t fl = x.flag;
@@ -1482,7 +1539,7 @@ __device__ void stage_filter(const sbt_params &PP, const Ev &v0, int n_fin, cons
         }
         if (fl == kFlagAccepted) at(v.link(), 2u * R.key + 1u) = (uint16_t)r;
     }
-    __syncthreads();
+    ev_sync<B>();
 }
 
 // ---------------------------------------------------------------- per-event compaction
@@ -1510,8 +1567,8 @@ template <int B>
 __device__ void compact_lds(const Ev &v, int *s_scan, int lds_bytes)
 {
     const int N = v.N;
-    uint16_t *lprev = reinterpret_cast<uint16_t *>(g_lds);
-    uint16_t *lrec = reinterpret_cast<uint16_t *>(g_lds + a16(2u * (uint32_t)N));
+    uint16_t *lprev = reinterpret_cast<uint16_t *>(g_lds + v.lo);
+    uint16_t *lrec = reinterpret_cast<uint16_t *>(g_lds + v.lo + a16(2u * (uint32_t)N));
     const int rec_cap = (lds_bytes - (int)a16(2u * (uint32_t)N)) / 2;
     const uint32_t *link = reinterpret_cast<const uint32_t *>(v.link());   // prev | record << 16
     const int rounds = (N + B - 1) / B;
@@ -1521,13 +1578,13 @@ __device__ void compact_lds(const Ev &v, int *s_scan, int lds_bytes)
         uint32_t w[kCompactBatch];
 #pragma unroll
         for (int u = 0; u < kCompactBatch; ++u) {
-            const int k = (j0 + u) * B + (int)threadIdx.x;
+            const int k = (j0 + u) * B + (int)tid<B>();
             w[u] = k < N ? at(link, (uint32_t)k) : ((uint32_t)kNone << 16);
         }
 #pragma unroll
         for (int u = 0; u < kCompactBatch; ++u) {
             if (j0 + u >= rounds) break;
-            const int k = (j0 + u) * B + (int)threadIdx.x;
+            const int k = (j0 + u) * B + (int)tid<B>();
             const uint16_t r = (uint16_t)(w[u] >> 16);
             if (k < N) lprev[k] = (uint16_t)(w[u] & 0xFFFFu);
             int tot;
@@ -1539,11 +1596,11 @@ __device__ void compact_lds(const Ev &v, int *s_scan, int lds_bytes)
             nt += tot & 0xFFFF;
         }
     }
-    __syncthreads();   // links and the record list visible
+    ev_sync<B>();   // links and the record list visible
     if (nt > rec_cap) nt = 0;
     int nh = 0;
     for (int t0 = 0; t0 < nt; t0 += B) {
-        const int t = t0 + (int)threadIdx.x;
+        const int t = t0 + (int)tid<B>();
         Rec R;
         int len = 0;
         if (t < nt) {
@@ -1574,7 +1631,7 @@ __device__ void compact_lds(const Ev &v, int *s_scan, int lds_bytes)
         }
     }
     if (bad) v.info().st = (int)SBT_EV_INTERNAL;
-    if (threadIdx.x == 0) {
+    if (tid<B>() == 0) {
         v.info().nt = nh <= N ? nt : 0;
         v.info().nh = nh <= N ? nh : 0;
     }
@@ -1588,7 +1645,7 @@ __device__ void compact_mem(const Ev &v, int *s_scan)
 {
     const int N = v.N;
     const int per = (N + B - 1) / B;
-    const int k0 = min(N, (int)threadIdx.x * per), k1 = min(N, k0 + per);
+    const int k0 = min(N, (int)tid<B>() * per), k1 = min(N, k0 + per);
     int nt = 0, nh = 0;
     for (int k = k0; k < k1; ++k) {
         const uint16_t r = at(v.link(), 2u * k + 1u);
@@ -1624,7 +1681,7 @@ __device__ void compact_mem(const Ev &v, int *s_scan)
         hi += R.len;
     }
     if (bad) v.info().st = (int)SBT_EV_INTERNAL;
-    if (threadIdx.x == 0) {
+    if (tid<B>() == 0) {
         v.info().nt = th <= N ? tt : 0;
         v.info().nh = th <= N ? th : 0;
     }

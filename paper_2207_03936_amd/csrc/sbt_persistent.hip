@@ -13,10 +13,28 @@
 
 using namespace sbt;
 
+// One event per group of B lanes.  For B > 64 the group is the workgroup and
+// its static LDS holds the event's Shared block.  For B = 64 a workgroup of
+// any number of waves runs one event per wave, each with its own region of
+// the dynamic LDS (the Shared block, then the layout of lds_bytes(CAP,
+// own_cap) bytes), and no wave ever waits for another.
 template <int B, int CAP>
-__global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work W0, int own_cap, int sortcap)
+__global__ __launch_bounds__(B == 64 ? 64 * kMaxEventsPerBlock : B) void k_persistent(sbt_params P, HitsArgs H,
+                                                                                     Work W0, int own_cap,
+                                                                                     int sortcap)
 {
-    __shared__ Shared<B> S;
+    uint32_t lo = 0;
+    Shared<B> *sp;
+    if constexpr (B == 64) {
+        const uint32_t region = event_region_bytes<B>(CAP, own_cap);
+        const uint32_t r0 = (uint32_t)uni((int)(threadIdx.x >> 6)) * region;
+        sp = reinterpret_cast<Shared<B> *>(g_lds + r0);
+        lo = r0 + shared_block_bytes<B>();
+    } else {
+        __shared__ Shared<B> S_wg;
+        sp = &S_wg;
+    }
+    Shared<B> &S = *sp;
     for (;;) {
         // the workspace base is hidden from the optimiser per event, so the
         // pointers derived from it are not hoisted out of this loop
@@ -24,29 +42,29 @@ __global__ __launch_bounds__(B) void k_persistent(sbt_params P, HitsArgs H, Work
         W.base = opq_global(W0.base);
         W.H = opq(W0.H);
         W.E = opq(W0.E);
-        if (threadIdx.x == 0) {
+        if (tid<B>() == 0) {
             const int idx = (int)atomicAdd(ws_counterp(W), 1u);
             S.e = idx < H.n_events ? ws_orderp(W)[idx] : -1;
         }
-        __syncthreads();
+        ev_sync<B>();
         const int e = uni(S.e);
         if (e < 0) break;
         int hb, N;
         const int st = load_event<B>(P, H, e, S, &hb, &N);
-        if (threadIdx.x == 0) ws_evinfo(W)[e].st = st;
+        if (tid<B>() == 0) ws_evinfo(W)[e].st = st;
         if (st == 0) {
-            const Ev v = event_view(W, e, hb, N);
+            const Ev v = event_view(W, e, hb, N, lo);
             stage_sort<B>(P, H, v, S, sortcap);
             const bool in_lds = stage_track<B, CAP>(P, v, S, own_cap, false);
             const int n_fin = uni(S.cnt[3]);
-            if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own());
+            if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own(v.lo));
             else stage_filter<B>(P, v, n_fin, v.own());
             stage_compact<B>(v, S.scan, (int)lds_sort_head() + 4 * sortcap);
-        } else if (threadIdx.x == 0) {
+        } else if (tid<B>() == 0) {
             ws_evinfo(W)[e].nt = 0;
             ws_evinfo(W)[e].nh = 0;
         }
-        __syncthreads();
+        ev_sync<B>();
     }
 }
 

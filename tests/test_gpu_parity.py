@@ -205,6 +205,52 @@ def test_batched_independent_of_launch_configuration(tpe, bpc):
     _same(got, want, f"tpe={tpe} bpc={bpc}")
 
 
+# 64-lane events several to a workgroup, one wave each: (events per
+# workgroup, slot capacity, LDS flag capacity, workgroups per CU).  Each
+# workgroup's LDS (the events' regions together) stays within 159 KiB.
+EPB_CASES = [(2, 256, 4096, 2), (4, 256, 4096, 1), (3, 448, 4096, 1), (8, 0, 4096, 1), (2, 672, 16384, 1),
+             (10, 0, 0, 2)]
+
+
+@pytest.mark.parametrize("epb,cap,own,bpc", EPB_CASES)
+def test_events_per_block_matches_oracle(epb, cap, own, bpc):
+    """Several 64-lane events per workgroup give the oracle's tracks on every
+    recipe: events whose modules or flags do not fit the LDS regions run from
+    memory beside ones that do, and batches with fewer events than waves
+    leave waves without work."""
+    say(f"events per block {epb}, cap={cap} own={own} bpc={bpc}")
+    for config, n, first in (("mu7.6", 24, 100), ("tiny", 40, 0), ("mu1-25", 30, 5), ("mu30", 4, 2), ("tiny", 3, 9)):
+        b = synth.make_batch(config, n, first=first)
+        want = oracle.reconstruct(b)
+        t = sbt.make_tuning(64, bpc, cap, own, events_per_block=epb)
+        got = run_batched(b, t)
+        assert not got[3].any()
+        _same(got, want, f"epb={epb} cap={cap} {config} x{n}")
+
+
+def test_events_per_block_graph_replays_and_tuning_checks():
+    """The grouped configuration through the captured graph (three calls,
+    two replays) gives the oracle's tracks; more than one event per
+    workgroup is refused for events wider than one wave, and so is a
+    workgroup whose LDS would exceed 159 KiB."""
+    import torch
+    b = synth.make_batch("mu1-25", 40, first=11)
+    want = oracle.reconstruct(b)
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits, sbt.make_tuning(64, 1, 256, 4096, events_per_block=4))
+    assert ctx.get_tuning().as_dict()["events_per_block"] == 4
+    dev = sbt.DeviceBatch(b)
+    out = sbt.DeviceTracks(b.n_events, b.n_hits)
+    got, stats = graph_replays(ctx, dev, out, torch.cuda.Stream())
+    check_replays(got, stats, want, "events per block 4")
+    for bad in (sbt.make_tuning(128, 1, 256, 4096, events_per_block=2),
+                sbt.make_tuning(64, 1, 672, 16384, events_per_block=3),
+                sbt.make_tuning(64, 1, 256, 4096, events_per_block=17)):
+        with pytest.raises(sbt.SbtError):
+            ctx.set_tuning(bad)
+    ctx.close()
+
+
 # LDS capacities: 0 or 1 forces every module window / the owner flags to be
 # read from memory, intermediate values mix both within one event
 LDS_CASES = [(0, 0), (1, 1), (64, 1000), (200, 3000), (256, 16384), (448, 16384), (672, 16384),
@@ -644,9 +690,13 @@ def test_autotune_installs_a_candidate_and_keeps_results():
     t = ctx.get_tuning()
     say(f"  picked {t.as_dict()} at {ms:.3f} ms")
     assert t.as_dict() == best.as_dict()
-    assert t.threads_per_event in (128, 256, 512, 1024)
+    assert t.threads_per_event in (64, 128, 256, 512, 1024)
     assert t.lds_window_hits in (256, 448, 672, 768, 1024, 1536)
-    assert 1 <= t.blocks_per_cu <= 16 and t.lds_owner_hits == 16384
+    assert 1 <= t.blocks_per_cu <= 16
+    if t.threads_per_event == 64:
+        assert t.events_per_block in (2, 4, 8) and t.lds_window_hits in (256, 448) and t.lds_owner_hits == 4096
+    else:
+        assert t.events_per_block == 1 and t.lds_owner_hits == 16384
     assert ms > 0
     out = sbt.DeviceTracks(b.n_events, b.n_hits)
     got, stats = graph_replays(ctx, dev, out, stream, reps=2)
