@@ -534,8 +534,11 @@ def test_full_size_half_precision():
 
 
 def _expected_choice(n_events, n_hits, cus):
+    small = n_hits <= 2500 * n_events
     large = n_hits >= 4000 * n_events
     huge = n_hits >= 9000 * n_events
+    if small:
+        return (256, 5, 256) if n_events > 2 * cus else (512, 2, 448)
     if n_events <= cus or (n_events <= 2 * cus and large) or huge:
         return (1024, 1, 1536)
     if not large and n_events > 12 * cus:
@@ -544,7 +547,7 @@ def _expected_choice(n_events, n_hits, cus):
 
 
 @pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000),
-                                      ("mu7.6", 3600), ("mu30", 600)])
+                                      ("mu7.6", 3600), ("mu30", 600), ("tiny", 100), ("tiny", 700)])
 def test_configuration_chosen_per_call(config, n):
     """A context created without a launch configuration chooses one per call
     from the batch's size.  Each choice, a smaller batch through the same
