@@ -21,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sbt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_ABI_H = os.path.join(_HERE, "sbt_oracle_abi.h")
 _lib = None
 
 # default tolerances (also used by the HIP path's callers); see the design notes
@@ -50,7 +51,8 @@ def build() -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                    os.path.getmtime(_ABI_H)):
             build()
         L = ctypes.CDLL(_LIB)
         f32p = ctypes.POINTER(ctypes.c_float)
@@ -69,6 +71,9 @@ def lib():
                                           ctypes.c_int32, i32p]
         L.sbt_oracle_tracklet_chi2.restype = ctypes.c_float
         L.sbt_oracle_tracklet_chi2.argtypes = [f32p, f32p, f32p]
+        L.sbt_reconstruct_cpu.restype = ctypes.c_int
+        L.sbt_reconstruct_cpu.argtypes = [ctypes.POINTER(OrcAbiParams), ctypes.POINTER(OrcAbiHits),
+                                          ctypes.POINTER(OrcAbiTracks)]
         L.sbt_oracle_reconstruct.restype = ctypes.c_int
         L.sbt_oracle_reconstruct.argtypes = (
             [ctypes.c_int32, f32p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -76,6 +81,28 @@ def lib():
              ctypes.c_int32, i32p, i32p, f32p, f32p, f32p, i32p, i32p, i32p])
         _lib = L
     return _lib
+
+
+class OrcAbiParams(ctypes.Structure):
+    """orc_abi_params of sbt_oracle_abi.h."""
+    _fields_ = [("n_modules", ctypes.c_int32), ("module_z", ctypes.c_float * 64), ("reverse", ctypes.c_int32),
+                ("max_doublet_candidates", ctypes.c_int32), ("phi_window_seeding", ctypes.c_int32),
+                ("phi_window_forwarding", ctypes.c_int32), ("max_scatter_seeding", ctypes.c_float),
+                ("max_scatter_forwarding", ctypes.c_float), ("max_tracklet_chi2", ctypes.c_float),
+                ("max_consecutive_misses", ctypes.c_int32), ("max_event_hits", ctypes.c_int32)]
+
+
+class OrcAbiHits(ctypes.Structure):
+    """orc_abi_hits of sbt_oracle_abi.h (host pointers)."""
+    _fields_ = [("n_events", ctypes.c_int32), ("n_hits", ctypes.c_int32),
+                ("event_offsets", ctypes.c_void_p), ("module_offsets", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("z", ctypes.c_void_p)]
+
+
+class OrcAbiTracks(ctypes.Structure):
+    """orc_abi_tracks of sbt_oracle_abi.h (host pointers)."""
+    _fields_ = [("event_track_offsets", ctypes.c_void_p), ("track_hit_offsets", ctypes.c_void_p),
+                ("track_hits", ctypes.c_void_p), ("event_status", ctypes.c_void_p)]
 
 
 def _p(a, ct):
@@ -150,3 +177,39 @@ def reconstruct(batch, **overrides):
         raise RuntimeError(f"oracle reconstruct failed: {rc}")
     T = int(eto[-1])
     return eto, tho[:T + 1].copy(), th[:int(tho[T])].copy()
+
+
+def reconstruct_abi(batch, **overrides):
+    """The same reconstruction through the structure entry point
+    (sbt_reconstruct_cpu), which also checks every event's offsets and size
+    and reports them per event.  Returns (event_track_offsets,
+    track_hit_offsets, track_hits, event_status) as int32 numpy arrays,
+    trimmed."""
+    p = dict(DEFAULTS)
+    p.update(overrides)
+    mz = np.ascontiguousarray(batch.module_z, dtype=np.float32)
+    eo = np.ascontiguousarray(batch.event_offsets, dtype=np.int32)
+    mo = np.ascontiguousarray(batch.module_offsets, dtype=np.int32)
+    x = np.ascontiguousarray(batch.x, dtype=np.float32)
+    y = np.ascontiguousarray(batch.y, dtype=np.float32)
+    z = np.ascontiguousarray(batch.z, dtype=np.float32)
+    E, H = int(eo.size - 1), int(x.size)
+    prm = OrcAbiParams()
+    prm.n_modules = int(mz.size)
+    for k, v in enumerate(mz):
+        prm.module_z[k] = float(v)
+    for key in ("reverse", "max_doublet_candidates", "phi_window_seeding", "phi_window_forwarding",
+                "max_scatter_seeding", "max_scatter_forwarding", "max_tracklet_chi2", "max_consecutive_misses",
+                "max_event_hits"):
+        setattr(prm, key, p[key])
+    hits = OrcAbiHits(E, H, eo.ctypes.data, mo.ctypes.data, x.ctypes.data, y.ctypes.data, z.ctypes.data)
+    eto = np.zeros(E + 1, dtype=np.int32)
+    tho = np.zeros(H // 3 + 1, dtype=np.int32)
+    th = np.zeros(max(H, 1), dtype=np.int32)
+    st = np.zeros(max(E, 1), dtype=np.int32)
+    out = OrcAbiTracks(eto.ctypes.data, tho.ctypes.data, th.ctypes.data, st.ctypes.data)
+    rc = lib().sbt_reconstruct_cpu(ctypes.byref(prm), ctypes.byref(hits), ctypes.byref(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle reconstruct failed: {rc}")
+    T = int(eto[-1])
+    return eto, tho[:T + 1].copy(), th[:int(tho[T])].copy(), st[:E].copy()

@@ -48,6 +48,8 @@
 #include <string.h>
 #include <math.h>
 
+#include "sbt_oracle_abi.h"
+
 #define ORC_OK 0
 #define ORC_ERR_INVALID_ARG (-1)
 #define ORC_ERR_NOMEM (-5)
@@ -409,7 +411,7 @@ static int32_t orc_event_run(const orc_params *p, int N, const int32_t *mo,
     orc_event ev;
     memset(&ev, 0, sizeof ev);
     ev.N = N; ev.M = p->M; ev.mo = mo; ev.x = x; ev.y = y; ev.z = z;
-    ev.q = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)N);
+    ev.q = (uint16_t *)calloc((size_t)N, sizeof(uint16_t));   /* every entry is written below */
     ev.sorted = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     ev.owner = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)N);
     ev.claim = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)N);
@@ -532,6 +534,66 @@ int sbt_oracle_reconstruct(int32_t n_modules, const float *module_z, int32_t rev
         n_tracks += nt;
         n_out_hits += nh;
         event_track_offsets[e + 1] = n_tracks;
+    }
+    return ORC_OK;
+}
+
+/* Batch entry with the structure layouts of sbt_oracle_abi.h: the per-event
+ * status checks stated there, then the same per-event reconstruction as
+ * sbt_oracle_reconstruct for every event that passes them. */
+int sbt_reconstruct_cpu(const orc_abi_params *params, const orc_abi_hits *hits, orc_abi_tracks *tracks)
+{
+    if (!params || !hits || !tracks) return ORC_ERR_INVALID_ARG;
+    const orc_abi_params *q = params;
+    const int32_t M = q->n_modules, E = hits->n_events, H = hits->n_hits;
+    if (M < 3 || M > ORC_MAX_MODULES || E < 0 || H < 0) return ORC_ERR_INVALID_ARG;
+    if (q->max_doublet_candidates < 1 || q->max_consecutive_misses < 0 || q->max_event_hits < 0)
+        return ORC_ERR_INVALID_ARG;
+    if (q->phi_window_seeding < 0 || q->phi_window_seeding > 32767) return ORC_ERR_INVALID_ARG;
+    if (q->phi_window_forwarding < 0 || q->phi_window_forwarding > 32767) return ORC_ERR_INVALID_ARG;
+    if (!tracks->event_track_offsets || !tracks->track_hit_offsets || (H > 0 && !tracks->track_hits))
+        return ORC_ERR_INVALID_ARG;
+    if (E > 0 && (!hits->event_offsets || !hits->module_offsets)) return ORC_ERR_INVALID_ARG;
+    if (H > 0 && (!hits->x || !hits->y || !hits->z)) return ORC_ERR_INVALID_ARG;
+    orc_params p;
+    p.M = M; p.module_z = q->module_z; p.reverse = q->reverse ? 1 : 0;
+    p.K = q->max_doublet_candidates; p.Ws = q->phi_window_seeding; p.Wf = q->phi_window_forwarding;
+    p.Ss = q->max_scatter_seeding; p.Sf = q->max_scatter_forwarding; p.X = q->max_tracklet_chi2;
+    p.misses = q->max_consecutive_misses;
+
+    const int32_t *eo = hits->event_offsets, *mog = hits->module_offsets;
+    int32_t mo[ORC_MAX_MODULES + 1];
+    int32_t n_tracks = 0, n_out_hits = 0;
+    tracks->event_track_offsets[0] = 0;
+    tracks->track_hit_offsets[0] = 0;
+    for (int32_t e = 0; e < E; ++e) {
+        const int32_t lo = eo[e], hi = eo[e + 1];
+        int32_t st = 0;
+        if (lo < 0 || hi > H || hi < lo) st = ORC_EV_BAD_OFFSETS;
+        else if (hi - lo > 65535) st = ORC_EV_TOO_LARGE;
+        else if (q->max_event_hits > 0 && hi - lo > q->max_event_hits) st = ORC_EV_CUT;
+        else {
+            const int64_t b = (int64_t)e * M;
+            for (int32_t k = 0; k <= M; ++k) {
+                const int32_t v = mog[b + k];
+                if ((k == 0 && v != lo) || (k == M && v != hi) || v < lo || v > hi || (k > 0 && mog[b + k - 1] > v))
+                    st = ORC_EV_BAD_OFFSETS;
+            }
+        }
+        if (tracks->event_status) tracks->event_status[e] = st;
+        if (st == 0) {
+            for (int32_t k = 0; k <= M; ++k) mo[k] = mog[(int64_t)e * M + k] - lo;
+            int32_t nh = 0;
+            const int32_t nt = orc_event_run(&p, hi - lo, mo, hits->x + lo, hits->y + lo, hits->z + lo,
+                                             tracks->track_hit_offsets + n_tracks + 1,
+                                             tracks->track_hits + n_out_hits, &nh);
+            if (nt < 0) return nt;
+            for (int32_t i = 0; i < nt; ++i)
+                tracks->track_hit_offsets[n_tracks + 1 + i] += tracks->track_hit_offsets[n_tracks + i];
+            n_tracks += nt;
+            n_out_hits += nh;
+        }
+        tracks->event_track_offsets[e + 1] = n_tracks;
     }
     return ORC_OK;
 }
