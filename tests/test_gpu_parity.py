@@ -267,6 +267,47 @@ def test_lds_overflow_fallbacks(cap, own, config, n):
         _same(run_batched(b, sbt.make_tuning(tpe, 2, cap, own)), want, f"cap={cap} own={own} tpe={tpe}")
 
 
+def test_random_batches_and_launch_configurations():
+    """Seeded random draws of recipe, batch slice, launch configuration (any
+    width, workgroups per CU, slot and flag capacities, several 64-lane
+    events per workgroup) and call path (direct or captured graph): every
+    result is the oracle's.  Configurations the library refuses (LDS above
+    159 KiB) are skipped."""
+    import torch
+    rng = np.random.default_rng(2207)
+    stream = torch.cuda.Stream()
+    ran = 0
+    for i in range(40):
+        config = str(rng.choice(["tiny", "mu7.6", "mu1-25", "mu30", "pairs7.6", "bw7.6"]))
+        n = int(rng.integers(1, 6 if config == "mu30" else 30))
+        first = int(rng.integers(0, 200))
+        tpe = int(rng.choice([64, 128, 256, 512, 1024]))
+        epb = int(rng.choice([1, 2, 4])) if tpe == 64 else 1
+        t = sbt.make_tuning(tpe, int(rng.integers(1, 9)), int(rng.choice([0, 200, 256, 448, 672, 768, 1024, 1536])),
+                            int(rng.choice([0, 1000, 4096, 16384])), events_per_block=epb)
+        graph = bool(rng.integers(0, 2))
+        b = synth.make_batch(config, n, first=first)
+        p = sbt.make_params(b.module_z)
+        try:
+            ctx = sbt.Context(p, b.n_events, b.n_hits, t)
+        except sbt.SbtError:
+            continue
+        say(f"random {i}: {config} x{n} from {first}, {t.as_dict()}, graph={graph}")
+        out = sbt.DeviceTracks(b.n_events, b.n_hits)
+        if graph:
+            with torch.cuda.stream(stream):
+                ctx.reconstruct(sbt.DeviceBatch(b), out, stream)
+            stream.synchronize()
+        else:
+            ctx.reconstruct(sbt.DeviceBatch(b), out)
+        got = out.to_host()
+        ctx.close()
+        assert not got[3].any()
+        _same(got, oracle.reconstruct(b), f"random {i}")
+        ran += 1
+    assert ran >= 25
+
+
 def test_random_tiny_events_and_parameters():
     """Crowded tiny events with random tolerances, traversal direction and
     miss allowance: the same events the oracle's brute-force pins use."""
