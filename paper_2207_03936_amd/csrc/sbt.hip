@@ -144,6 +144,7 @@ __global__ __launch_bounds__(B) void k_compact(HitsArgs H, Work W, int lds_bytes
 // processing never changes an event's result).  Counting sort on N / 64.
 constexpr int kOrderThreads = 256;    // small, so it fits beside another stream's persistent workgroups
 constexpr int kOrderClasses = 1024;
+constexpr int kOrderBatch = 4;        // events whose offsets a lane loads together
 __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 {
     __shared__ int hist[kOrderClasses + 1];
@@ -154,21 +155,33 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
     for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) fill[i] = 0;
     __syncthreads();
     const int E = H.n_events;
-    for (int e = threadIdx.x; e < E; e += kOrderThreads) {
-        int n = H.eo[e + 1] - H.eo[e];
+    // bucket of event e (largest first), -1 past the end; a lane loads the
+    // offsets of kOrderBatch events before using them
+    auto bucket = [&](int e) -> int {
+        if (e >= E) return -1;
+        const int n = H.eo[e + 1] - H.eo[e];
         int cls = n < 0 ? 0 : (n >> 6);
         cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
-        atomicAdd(&hist[kOrderClasses - 1 - cls], 1);
+        return kOrderClasses - 1 - cls;
+    };
+    for (int e0 = threadIdx.x; e0 < E; e0 += kOrderBatch * kOrderThreads) {
+        int k[kOrderBatch];
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; ++j) k[j] = bucket(e0 + j * kOrderThreads);
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; ++j)
+            if (k[j] >= 0) atomicAdd(&hist[k[j]], 1);
     }
     __syncthreads();
     block_scan_inplace<kOrderThreads>(hist, kOrderClasses + 1, sw);
     __syncthreads();
-    for (int e = threadIdx.x; e < E; e += kOrderThreads) {
-        int n = H.eo[e + 1] - H.eo[e];
-        int cls = n < 0 ? 0 : (n >> 6);
-        cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
-        const int k = kOrderClasses - 1 - cls;
-        ws_orderp(W)[hist[k] + atomicAdd(&fill[k], 1)] = e;
+    for (int e0 = threadIdx.x; e0 < E; e0 += kOrderBatch * kOrderThreads) {
+        int k[kOrderBatch];
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; ++j) k[j] = bucket(e0 + j * kOrderThreads);
+#pragma unroll
+        for (int j = 0; j < kOrderBatch; ++j)
+            if (k[j] >= 0) ws_orderp(W)[hist[k[j]] + atomicAdd(&fill[k[j]], 1)] = e0 + j * kOrderThreads;
     }
 }
 
@@ -176,6 +189,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
 
 // exclusive scan over events of the per-event track and hit counts
 constexpr int kScanThreads = 256;     // small, so it fits beside another stream's persistent workgroups
+constexpr int kScanBatch = 8;         // events whose counts a lane loads together
 __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutArgs O)
 {
     const int E = H.n_events;
@@ -183,20 +197,40 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutAr
     const int chunk = (E + kScanThreads - 1) / kScanThreads;
     const int beg = threadIdx.x * chunk;
     const int end = min(beg + chunk, E);
+    EvInfo *ev = ws_evinfo(W);
+    // a lane's counts (nt, nh: one 8-byte load per event), kScanBatch of
+    // them in flight at once
+    auto counts = [&](int i) -> int2 {
+        return i < end ? *reinterpret_cast<const int2 *>(&ev[i].nt) : make_int2(0, 0);
+    };
     int st = 0, sh = 0;
-    for (int i = beg; i < end; ++i) {
-        st += ws_evinfo(W)[i].nt;
-        sh += ws_evinfo(W)[i].nh;
+    for (int i0 = beg; i0 < end; i0 += kScanBatch) {
+        int2 c[kScanBatch];
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) c[k] = counts(i0 + k);
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) {
+            st += c[k].x;
+            sh += c[k].y;
+        }
     }
     int tt, th;
     int ot = block_excl_scan<kScanThreads>(st, sw, 0, &tt);
     int oh = block_excl_scan<kScanThreads>(sh, sw, 1, &th);
-    for (int i = beg; i < end; ++i) {
-        O.eto[i] = ot;
-        ws_evinfo(W)[i].out_t = ot;
-        ws_evinfo(W)[i].out_h = oh;
-        ot += ws_evinfo(W)[i].nt;
-        oh += ws_evinfo(W)[i].nh;
+    for (int i0 = beg; i0 < end; i0 += kScanBatch) {
+        int2 c[kScanBatch];
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) c[k] = counts(i0 + k);
+#pragma unroll
+        for (int k = 0; k < kScanBatch; ++k) {
+            if (i0 + k < end) {
+                O.eto[i0 + k] = ot;
+                ev[i0 + k].out_t = ot;
+                ev[i0 + k].out_h = oh;
+                ot += c[k].x;
+                oh += c[k].y;
+            }
+        }
     }
     if (threadIdx.x == 0) {
         O.eto[E] = tt;
