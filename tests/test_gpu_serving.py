@@ -92,13 +92,18 @@ def test_served_results_equal_alone(coords_f16):
         assert td >= ts
 
 
-def test_served_equals_plain_path_on_same_events():
-    say("serving vs plain path")
+@pytest.mark.parametrize("grouped", [False, True])
+def test_served_equals_plain_path_on_same_events(grouped):
+    """Served results equal the plain form's, with the server's per-launch
+    configuration or with an installed one that runs several 64-lane events
+    per workgroup."""
+    say(f"serving vs plain path, grouped events {grouped}")
     b = synth.make_batch("mu7.6", 40, first=500)
     params = sbt.make_params(b.module_z)
     plain = sbt.sbt_reconstruct(params, sbt.DeviceBatch(b)).to_host()
+    tuning = sbt.make_tuning(64, 2, 448, 4096, events_per_block=3) if grouped else None
     srv = sbt.Server(params, device_budget_bytes=1 << 30, n_slots=2, slot_events=7, slot_hits=1 << 16,
-                     max_wait_us=0)
+                     max_wait_us=0, tuning=tuning)
     for e in range(b.n_events):
         assert srv.submit(100 + e, *_event(b, e)) == 0
     got = _drain(srv, b.n_events)
