@@ -164,10 +164,17 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
         cls = cls > kOrderClasses - 1 ? kOrderClasses - 1 : cls;
         return kOrderClasses - 1 - cls;
     };
+    // the buckets of a lane's first kOrderBatch events stay in registers for
+    // the second pass (all of them when E <= kOrderBatch * kOrderThreads)
+    int kf[kOrderBatch];
     for (int e0 = threadIdx.x; e0 < E; e0 += kOrderBatch * kOrderThreads) {
         int k[kOrderBatch];
 #pragma unroll
         for (int j = 0; j < kOrderBatch; ++j) k[j] = bucket(e0 + j * kOrderThreads);
+        if (e0 == (int)threadIdx.x) {
+#pragma unroll
+            for (int j = 0; j < kOrderBatch; ++j) kf[j] = k[j];
+        }
 #pragma unroll
         for (int j = 0; j < kOrderBatch; ++j)
             if (k[j] >= 0) atomicAdd(&hist[k[j]], 1);
@@ -178,7 +185,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
     for (int e0 = threadIdx.x; e0 < E; e0 += kOrderBatch * kOrderThreads) {
         int k[kOrderBatch];
 #pragma unroll
-        for (int j = 0; j < kOrderBatch; ++j) k[j] = bucket(e0 + j * kOrderThreads);
+        for (int j = 0; j < kOrderBatch; ++j) k[j] = e0 == (int)threadIdx.x ? kf[j] : bucket(e0 + j * kOrderThreads);
 #pragma unroll
         for (int j = 0; j < kOrderBatch; ++j)
             if (k[j] >= 0) ws_orderp(W)[hist[k[j]] + atomicAdd(&fill[k[j]], 1)] = e0 + j * kOrderThreads;
@@ -203,11 +210,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutAr
     auto counts = [&](int i) -> int2 {
         return i < end ? *reinterpret_cast<const int2 *>(&ev[i].nt) : make_int2(0, 0);
     };
+    // the counts of a lane's first kScanBatch events stay in registers for
+    // the second pass (all of them when E <= kScanBatch * kScanThreads)
+    int2 cf[kScanBatch];
     int st = 0, sh = 0;
     for (int i0 = beg; i0 < end; i0 += kScanBatch) {
         int2 c[kScanBatch];
 #pragma unroll
         for (int k = 0; k < kScanBatch; ++k) c[k] = counts(i0 + k);
+        if (i0 == beg) {
+#pragma unroll
+            for (int k = 0; k < kScanBatch; ++k) cf[k] = c[k];
+        }
 #pragma unroll
         for (int k = 0; k < kScanBatch; ++k) {
             st += c[k].x;
@@ -220,7 +234,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(HitsArgs H, Work W, OutAr
     for (int i0 = beg; i0 < end; i0 += kScanBatch) {
         int2 c[kScanBatch];
 #pragma unroll
-        for (int k = 0; k < kScanBatch; ++k) c[k] = counts(i0 + k);
+        for (int k = 0; k < kScanBatch; ++k) c[k] = i0 == beg ? cf[k] : counts(i0 + k);
 #pragma unroll
         for (int k = 0; k < kScanBatch; ++k) {
             if (i0 + k < end) {
