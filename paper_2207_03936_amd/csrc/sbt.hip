@@ -589,6 +589,17 @@ const void *persistent_kernel(int tpe, int cap)
     }
 }
 
+// The persistent kernel a tuning runs: three or more 512-lane workgroups per
+// CU with 448-hit slots take the instance held to six waves per SIMD (with
+// the default register budget only two fit a CU).
+const void *persistent_fn(const sbt_tuning &T)
+{
+    const int cap = effective_cap(T.lds_window_hits);
+    if (T.threads_per_event == 512 && T.blocks_per_cu >= 3)
+        if (const void *fn = persistent_kernel_512_dense(cap)) return fn;
+    return persistent_kernel(T.threads_per_event, cap);
+}
+
 int device_cus(int *cus)
 {
     int dev = 0;
@@ -608,7 +619,7 @@ int allow_lds(const void *fn, size_t bytes)
 // resident workgroups per CU of the persistent kernel under a tuning
 int persistent_occupancy(const sbt_tuning &T, int *occ)
 {
-    const void *fn = persistent_kernel(T.threads_per_event, effective_cap(T.lds_window_hits));
+    const void *fn = persistent_fn(T);
     if (!fn) return SBT_ERR_INVALID_ARG;
     const size_t lds = tuning_lds(T);
     if (int rc = allow_lds(fn, lds)) return rc;
@@ -643,7 +654,7 @@ int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &
     Work Wc = W;
     void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap};
     hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
-    HIP_TRY(hipLaunchKernel(persistent_kernel(T.threads_per_event, cap), dim3(grid), dim3(block_lanes(T)), args, lds,
+    HIP_TRY(hipLaunchKernel(persistent_fn(T), dim3(grid), dim3(block_lanes(T)), args, lds,
                             s));
     return SBT_OK;
 }
@@ -936,9 +947,13 @@ sbt_tuning default_tuning()
 // batches run 512 lanes, two workgroups per CU; batches of large events take
 // 768-hit slots (the largest that still fit two workgroups' LDS on a CU), so
 // that their busiest modules stay in LDS rather than in memory.  Batches of
-// more than twelve smaller events per CU are throughput-bound rather than
-// bound by their largest event, and run 256 lanes, three workgroups per CU,
-// with 448-hit slots: more events in flight on the lanes they use.  Batches
+// six or more mid-size events per CU are throughput-bound rather than bound
+// by their largest event, and run 512 lanes, three workgroups per CU, with
+// 448-hit slots (the instance held to six waves per SIMD): 1.05x the
+// throughput of two per CU on 1,536 mu = 7.6 events, 1.16-1.19x on 2,000 to
+// 8,000 (1,280: 0.98x); the
+// few events with a larger module run from memory, which a long batch hides
+// but a batch of 1,000 does not (0.62 ms against 0.45).  Batches
 // of very large events (9,000 hits or more on average) have modules beyond
 // the 768-hit slots, and run 1,024 lanes per event with 1,536-hit slots
 // whatever their number (mu = 30 x 2,000: 3.72 ms against 4.48 ms).
@@ -968,8 +983,7 @@ sbt_tuning size_tuning(int E, int H, int cus)
         t.lds_window_hits = 1536;
     } else if (large) {
         t.lds_window_hits = 768;
-    } else if (E > 12 * cus) {
-        t.threads_per_event = 256;
+    } else if (E >= 6 * cus) {
         t.blocks_per_cu = 3;
         t.lds_window_hits = 448;
     }
@@ -1269,6 +1283,9 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
         t.lds_owner_hits = cd.tpe == 64 ? 4096 : 16384;
         t.events_per_block = cd.epb;
         if (valid_tuning(t) != SBT_OK) continue;
+        // occupancy of the instance the most workgroups per CU would run
+        // (the six-waves one where it exists)
+        t.blocks_per_cu = 16;
         int occ = 0;
         if ((rc = persistent_occupancy(t, &occ))) break;
         if (occ < 1) continue;

@@ -16,5 +16,8 @@ const void *persistent_kernel_128(int cap);
 const void *persistent_kernel_256(int cap);
 const void *persistent_kernel_512(int cap);
 const void *persistent_kernel_1024(int cap);
+// the 512-lane kernel held to six waves per SIMD, for three workgroups per
+// compute unit; compiled for 448-hit slots only (nullptr otherwise)
+const void *persistent_kernel_512_dense(int cap);
 
 }  // namespace sbt

@@ -68,6 +68,55 @@ __global__ __launch_bounds__(B == 64 ? 64 * kMaxEventsPerBlock : B) void k_persi
     }
 }
 
+#if SBT_TPE == 512
+// The 512-lane kernel held to six waves per SIMD (at most 80 VGPRs), so that
+// three workgroups with 448-hit slots (49.5 KB of LDS each) share a compute
+// unit: more events in flight for long batches.  The body is k_persistent's
+// for B = 512, written out again: routing both kernels through one inlined
+// function changes the default kernel's generated code, which is kept as it
+// was measured.
+template <int CAP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent_dense(
+    sbt_params P, HitsArgs H, Work W0, int own_cap, int sortcap)
+{
+    constexpr int B = 512;
+    constexpr uint32_t lo = 0;
+    __shared__ Shared<B> S;
+    for (;;) {
+        // the workspace base is hidden from the optimiser per event, so the
+        // pointers derived from it are not hoisted out of this loop
+        Work W = W0;
+        W.base = opq_global(W0.base);
+        W.H = opq(W0.H);
+        W.E = opq(W0.E);
+        if (tid<B>() == 0) {
+            const int idx = (int)atomicAdd(ws_counterp(W), 1u);
+            S.e = idx < H.n_events ? ws_orderp(W)[idx] : -1;
+        }
+        ev_sync<B>();
+        const int e = uni(S.e);
+        if (e < 0) break;
+        int hb, N;
+        const int st = load_event<B>(P, H, e, S, &hb, &N);
+        if (tid<B>() == 0) ws_evinfo(W)[e].st = st;
+        if (st == 0) {
+            const Ev v = event_view(W, e, hb, N, lo);
+            stage_sort<B>(P, H, v, S, sortcap);
+            const bool in_lds = stage_track<B, CAP>(P, v, S, own_cap, false);
+            const int n_fin = uni(S.cnt[3]);
+            if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own(v.lo));
+            else stage_filter<B>(P, v, n_fin, v.own());
+            stage_compact<B>(v, S.scan, (int)lds_sort_head() + 4 * sortcap);
+        } else if (tid<B>() == 0) {
+            ws_evinfo(W)[e].nt = 0;
+            ws_evinfo(W)[e].nh = 0;
+        }
+        ev_sync<B>();
+    }
+}
+
+#endif
+
 #define SBT_CAT2(a, b) a##b
 #define SBT_CAT(a, b) SBT_CAT2(a, b)
 
@@ -86,5 +135,12 @@ const void *SBT_CAT(persistent_kernel_, SBT_TPE)(int cap)
     default: return nullptr;
     }
 }
+
+#if SBT_TPE == 512
+const void *persistent_kernel_512_dense(int cap)
+{
+    return cap == 448 ? reinterpret_cast<const void *>(k_persistent_dense<448>) : nullptr;
+}
+#endif
 
 }  // namespace sbt

@@ -205,6 +205,26 @@ def test_batched_independent_of_launch_configuration(tpe, bpc):
     _same(got, want, f"tpe={tpe} bpc={bpc}")
 
 
+@pytest.mark.parametrize("config,n,first", [("mu7.6", 40, 340), ("mu7.6", 30, 620), ("mu1-25", 40, 0), ("mu30", 4, 1),
+                                            ("tiny", 30, 0)])
+def test_six_waves_instance_matches_oracle(config, n, first):
+    """512 lanes at three workgroups per CU run the instance held to six
+    waves per SIMD; with 448-hit slots, events whose busiest module is larger
+    (two of the mu=7.6 slices hold one) run from memory beside the others.
+    Direct launch, then the captured graph."""
+    import torch
+    say(f"six-waves instance {config} x{n} from {first}")
+    b = synth.make_batch(config, n, first=first)
+    want = oracle.reconstruct(b)
+    _same(run_batched(b, sbt.make_tuning(512, 3, 448)), want, f"dense {config}")
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits, sbt.make_tuning(512, 3, 448))
+    got, stats = graph_replays(ctx, sbt.DeviceBatch(b), sbt.DeviceTracks(b.n_events, b.n_hits), torch.cuda.Stream(),
+                               reps=2)
+    check_replays(got, stats, want, f"dense {config} graph")
+    ctx.close()
+
+
 # 64-lane events several to a workgroup, one wave each: (events per
 # workgroup, slot capacity, LDS flag capacity, workgroups per CU).  Each
 # workgroup's LDS (the events' regions together) stays within 159 KiB.
@@ -582,8 +602,8 @@ def _expected_choice(n_events, n_hits, cus):
         return (256, 5, 256) if n_events > 2 * cus else (512, 2, 448)
     if n_events <= cus or (n_events <= 2 * cus and large) or huge:
         return (1024, 1, 1536)
-    if not large and n_events > 12 * cus:
-        return (256, 3, 448)
+    if not large and n_events >= 6 * cus:
+        return (512, 3, 448)
     return (512, 2, 768 if large else 672)
 
 
