@@ -105,13 +105,15 @@ def _summary(name, per_launch_hits: int, tuning: dict):
     return d
 
 
-TUNING_KEYS = ("threads_per_event", "blocks_per_cu", "lds_window_hits", "events_per_block")
+TUNING_KEYS = ("threads_per_event", "blocks_per_cu", "lds_window_hits", "events_per_block", "deferred_window_hits")
+_TUNING_DEFAULTS = {"events_per_block": 1, "deferred_window_hits": 0}
 
 
 def _tuning_key(t: dict):
     """The launch configuration a summary is valid for (events per workgroup
-    reads as 1 where a configuration does not name it)."""
-    return tuple(int(t.get(k, 1)) if k == "events_per_block" else t.get(k) for k in TUNING_KEYS)
+    reads as 1 and the second pass as none where a configuration does not
+    name them)."""
+    return tuple(int(t.get(k, _TUNING_DEFAULTS[k])) if k in _TUNING_DEFAULTS else t.get(k) for k in TUNING_KEYS)
 
 
 def measured_traffic(per_launch_hits: int, tuning: dict):

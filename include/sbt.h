@@ -189,6 +189,13 @@ typedef struct sbt_tracks {
  *                     64-lane event is one wave with its own LDS region and
  *                     takes its next event from the queue on its own, so the
  *                     waves of a workgroup never wait for one another.
+ * deferred_window_hits 0: events whose busiest module exceeds the slots run
+ *                     from memory.  > 0 (only with 512 lanes, three or more
+ *                     workgroups per CU and 448-hit slots, which run the
+ *                     kernel instance held to six waves per SIMD): such events
+ *                     are set aside and run in a second pass with slots of
+ *                     this many hits (512 lanes x 2 per CU, or 1,024 x 1 above
+ *                     768 hits).  Must exceed the first pass's slots.
  * The LDS of a workgroup (both capacities, times events_per_block for
  * 64-lane events) is at most 159 KiB.                                      */
 typedef struct sbt_tuning {
@@ -197,6 +204,7 @@ typedef struct sbt_tuning {
     int32_t lds_window_hits;
     int32_t lds_owner_hits;
     int32_t events_per_block;
+    int32_t deferred_window_hits;
 } sbt_tuning;
 
 /* Message for a return code (static storage). */

@@ -150,7 +150,10 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
     __shared__ int hist[kOrderClasses + 1];
     __shared__ int fill[kOrderClasses];
     __shared__ int sw[2 * (kOrderThreads / 64)];
-    if (threadIdx.x == 0) *ws_counterp(W) = 0u;
+    if (threadIdx.x == 0) {
+        *ws_counterp(W) = 0u;
+        *ws_defer_countp(W) = 0u;
+    }
     for (int i = threadIdx.x; i <= kOrderClasses; i += kOrderThreads) hist[i] = 0;
     for (int i = threadIdx.x; i < kOrderClasses; i += kOrderThreads) fill[i] = 0;
     __syncthreads();
@@ -190,6 +193,19 @@ __global__ __launch_bounds__(kOrderThreads) void k_prepare(HitsArgs H, Work W)
         for (int j = 0; j < kOrderBatch; ++j)
             if (k[j] >= 0) ws_orderp(W)[hist[k[j]] + atomicAdd(&fill[k[j]], 1)] = e0 + j * kOrderThreads;
     }
+}
+
+// Between the passes of a two-pass launch: the events the first pass set
+// aside (in the order it met them, largest first) move to the end of the event
+// order, and the work counter starts at them, so that the second pass runs
+// exactly those.
+constexpr int kDeferThreads = 256;
+__global__ __launch_bounds__(kDeferThreads) void k_defer(HitsArgs H, Work W)
+{
+    const int E = H.n_events;
+    const int D = (int)*ws_defer_countp(W);
+    for (int i = threadIdx.x; i < D; i += kDeferThreads) ws_orderp(W)[E - D + i] = ws_deferp(W)[i];
+    if (threadIdx.x == 0) *ws_counterp(W) = (unsigned int)(E - D);
 }
 
 // shared tail -----------------------------------------------------------------
@@ -639,8 +655,25 @@ int persistent_grid(const sbt_tuning &T, int n_events, int *grid)
     return SBT_OK;
 }
 
-// k_prepare and the persistent kernel: per-event track lists in the workspace
-int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W, hipStream_t s)
+// The configuration of the second pass of a two-pass tuning: the events set
+// aside, with slots of deferred_window_hits, on 512 lanes x 2 per CU (1,024
+// lanes x 1 above 768-hit slots, which two workgroups per CU cannot hold).
+sbt_tuning deferred_tuning(const sbt_tuning &T)
+{
+    sbt_tuning t = T;
+    const bool wide = effective_cap(T.deferred_window_hits) > 768;
+    t.threads_per_event = wide ? 1024 : 512;
+    t.blocks_per_cu = wide ? 1 : 2;
+    t.lds_window_hits = T.deferred_window_hits;
+    t.events_per_block = 1;
+    t.deferred_window_hits = 0;
+    return t;
+}
+
+// launch of one persistent pass (defer: set aside the events that do not fit
+// the LDS form; only the six-waves instance has that mode)
+int launch_pass(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W, hipStream_t s,
+                int defer)
 {
     int grid = 0;
     int rc = persistent_grid(T, H.n_events, &grid);
@@ -652,11 +685,24 @@ int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &
     sbt_params Pc = P;
     HitsArgs Hc = H;
     Work Wc = W;
-    void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap};
-    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
-    HIP_TRY(hipLaunchKernel(persistent_fn(T), dim3(grid), dim3(block_lanes(T)), args, lds,
-                            s));
+    // the six-waves instance takes one argument more (defer); the others read
+    // the first five
+    void *args[] = {&Pc, &Hc, &Wc, &own_cap, &sortcap, &defer};
+    HIP_TRY(hipLaunchKernel(persistent_fn(T), dim3(grid), dim3(block_lanes(T)), args, lds, s));
     return SBT_OK;
+}
+
+// k_prepare and the persistent kernel: per-event track lists in the workspace.
+// A two-pass tuning (deferred_window_hits > 0) runs the six-waves instance
+// first, setting aside the events its slots cannot hold, then those events
+// on larger slots.
+int launch_persistent(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_prepare, dim3(1), dim3(kOrderThreads), 0, s, H, W);
+    if (T.deferred_window_hits <= 0) return launch_pass(P, T, H, W, s, 0);
+    if (int rc = launch_pass(P, T, H, W, s, 1)) return rc;
+    hipLaunchKernelGGL(k_defer, dim3(1), dim3(kDeferThreads), 0, s, H, W);
+    return launch_pass(P, deferred_tuning(T), H, W, s, 0);
 }
 
 int launch_batched(const sbt_params &P, const sbt_tuning &T, const HitsArgs &H, const Work &W,
@@ -925,6 +971,14 @@ int valid_tuning(const sbt_tuning &t)
     if (t.events_per_block < 0 || t.events_per_block > kMaxEventsPerBlock) return SBT_ERR_INVALID_ARG;
     if (events_per_block(t) > 1 && t.threads_per_event != 64) return SBT_ERR_INVALID_ARG;
     if (tuning_lds(t) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
+    if (t.deferred_window_hits < 0 || t.deferred_window_hits > 2048) return SBT_ERR_INVALID_ARG;
+    if (t.deferred_window_hits > 0) {
+        // a first pass on the six-waves instance, a second on larger slots
+        if (t.threads_per_event != 512 || t.blocks_per_cu < 3 || !persistent_kernel_512_dense(effective_cap(t.lds_window_hits)))
+            return SBT_ERR_INVALID_ARG;
+        if (effective_cap(t.deferred_window_hits) <= effective_cap(t.lds_window_hits)) return SBT_ERR_INVALID_ARG;
+        if (tuning_lds(deferred_tuning(t)) > kMaxDynLds) return SBT_ERR_INVALID_ARG;
+    }
     return SBT_OK;
 }
 
@@ -936,6 +990,7 @@ sbt_tuning default_tuning()
     t.lds_window_hits = 672;
     t.lds_owner_hits = 16384;
     t.events_per_block = 1;
+    t.deferred_window_hits = 0;
     return t;
 }
 
@@ -953,7 +1008,12 @@ sbt_tuning default_tuning()
 // throughput of two per CU on 1,536 mu = 7.6 events, 1.16-1.19x on 2,000 to
 // 8,000 (1,280: 0.98x); the
 // few events with a larger module run from memory, which a long batch hides
-// but a batch of 1,000 does not (0.62 ms against 0.45).  Batches
+// but a batch of 1,000 does not (0.62 ms against 0.45).  Long batches of
+// large events (fifteen or more per CU) run the same way in two passes: the
+// events whose busiest module exceeds 448 hits (38 % of mu in U{1..25}) are
+// set aside and then run with 768-hit slots, two per CU (mu in U{1..25} x
+// 10,000: 5.59 ms against 6.03; x 4,000: 2.33 against 2.42; x 2,500: 1.58
+// against 1.54, so not below fifteen per CU).  Batches
 // of very large events (9,000 hits or more on average) have modules beyond
 // the 768-hit slots, and run 1,024 lanes per event with 1,536-hit slots
 // whatever their number (mu = 30 x 2,000: 3.72 ms against 4.48 ms).
@@ -981,6 +1041,10 @@ sbt_tuning size_tuning(int E, int H, int cus)
         t.threads_per_event = 1024;
         t.blocks_per_cu = 1;
         t.lds_window_hits = 1536;
+    } else if (large && E >= 15 * cus) {
+        t.blocks_per_cu = 3;
+        t.lds_window_hits = 448;
+        t.deferred_window_hits = 768;
     } else if (large) {
         t.lds_window_hits = 768;
     } else if (E >= 6 * cus) {
@@ -1266,13 +1330,14 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
     // workgroup for 64-lane events), each at the largest number of resident
     // workgroups per CU and one less
     struct Cand {
-        int tpe, cap, epb;
+        int tpe, cap, epb, deferred;
     };
     std::vector<Cand> cands;
     for (int tpe : {128, 256, 512, 1024})
-        for (int cap : {256, 448, 672, 768, 1024, 1536}) cands.push_back({tpe, cap, 1});
+        for (int cap : {256, 448, 672, 768, 1024, 1536}) cands.push_back({tpe, cap, 1, 0});
     for (int epb : {2, 4, 8})
-        for (int cap : {256, 448}) cands.push_back({64, cap, epb});
+        for (int cap : {256, 448}) cands.push_back({64, cap, epb, 0});
+    cands.push_back({512, 448, 1, 768});   // two passes: three per CU, then the events set aside
     sbt_tuning win = c->tuning;
     float win_ms = -1.0f;
     rc = SBT_OK;
@@ -1282,15 +1347,17 @@ int sbt_autotune(sbt_context *c, const sbt_hits *sample, sbt_tracks *tracks, voi
         t.lds_window_hits = cd.cap;
         t.lds_owner_hits = cd.tpe == 64 ? 4096 : 16384;
         t.events_per_block = cd.epb;
-        if (valid_tuning(t) != SBT_OK) continue;
+        t.deferred_window_hits = cd.deferred;
         // occupancy of the instance the most workgroups per CU would run
         // (the six-waves one where it exists)
         t.blocks_per_cu = 16;
+        if (valid_tuning(t) != SBT_OK) continue;
         int occ = 0;
         if ((rc = persistent_occupancy(t, &occ))) break;
         if (occ < 1) continue;
         for (int bpc = occ; bpc >= 1 && bpc >= occ - 1; --bpc) {
             t.blocks_per_cu = bpc;
+            if (valid_tuning(t) != SBT_OK) continue;   // a two-pass tuning needs three per CU
             if ((rc = launch_batched(c->params, t, H, c->W, O, s, nullptr))) break;   // warm-up
             if (hipEventRecord(t0, s) != hipSuccess) { rc = SBT_ERR_HIP; break; }
             for (int r = 0; r < reps && rc == SBT_OK; ++r) rc = launch_batched(c->params, t, H, c->W, O, s, nullptr);

@@ -85,7 +85,8 @@ constexpr int kLists = 6;
 // keys of events too large for the LDS sort), link 4, st_toff 4 (per-event
 // track hit offsets), six u16 lists 12, st_hits 2 (per-event compacted hit
 // ids).  Then the flag bitmaps (event e's starts at word (hb >> 5) + e), the
-// per-event counters, the event order (largest first) and the work counter.
+// per-event counters, the event order (largest first), the work counter (and
+// beside it the count of events set aside) and the list of events set aside.
 struct Work {
     char *base;
     uint32_t H, E;
@@ -98,7 +99,9 @@ __host__ __device__ inline uint64_t ws_owner(uint32_t H) { return (uint64_t)H * 
 __host__ __device__ inline uint64_t ws_ev(uint32_t H, uint32_t E) { return ws_owner(H) + (((uint64_t)H / 32 + E + 2) * 4 + 255) / 256 * 256; }
 __host__ __device__ inline uint64_t ws_order(uint32_t H, uint32_t E) { return ws_ev(H, E) + (uint64_t)E * 32; }
 __host__ __device__ inline uint64_t ws_counter(uint32_t H, uint32_t E) { return ws_order(H, E) + (uint64_t)E * 4; }
-__host__ __device__ inline uint64_t ws_bytes(uint32_t H, uint32_t E) { return ws_counter(H, E) + 256; }
+// events a first pass set aside for a second one
+__host__ __device__ inline uint64_t ws_defer(uint32_t H, uint32_t E) { return ws_counter(H, E) + 256; }
+__host__ __device__ inline uint64_t ws_bytes(uint32_t H, uint32_t E) { return ws_defer(H, E) + ((uint64_t)E * 4 + 255) / 256 * 256; }
 
 __host__ __device__ inline EvInfo *ws_evinfo(const Work &W) { return (EvInfo *)(W.base + ws_ev(W.H, W.E)); }
 __host__ __device__ inline int32_t *ws_orderp(const Work &W) { return (int32_t *)(W.base + ws_order(W.H, W.E)); }
@@ -106,6 +109,9 @@ __host__ __device__ inline unsigned int *ws_counterp(const Work &W)
 {
     return (unsigned int *)(W.base + ws_counter(W.H, W.E));
 }
+// the number of events set aside, beside the work counter
+__host__ __device__ inline unsigned int *ws_defer_countp(const Work &W) { return ws_counterp(W) + 1; }
+__host__ __device__ inline int32_t *ws_deferp(const Work &W) { return (int32_t *)(W.base + ws_defer(W.H, W.E)); }
 __host__ __device__ inline Hit16 *ws_hs(const Work &W) { return (Hit16 *)(W.base + (uint64_t)W.H * kOffHs); }
 __host__ __device__ inline int32_t *ws_toff(const Work &W) { return (int32_t *)(W.base + (uint64_t)W.H * kOffToff); }
 __host__ __device__ inline uint16_t *ws_sthits(const Work &W)

@@ -71,13 +71,15 @@ __global__ __launch_bounds__(B == 64 ? 64 * kMaxEventsPerBlock : B) void k_persi
 #if SBT_TPE == 512
 // The 512-lane kernel held to six waves per SIMD (at most 80 VGPRs), so that
 // three workgroups with 448-hit slots (49.5 KB of LDS each) share a compute
-// unit: more events in flight for long batches.  The body is k_persistent's
+// unit: more events in flight for long batches.  With defer, events whose
+// busiest module or flag count does not fit the LDS form are not run from
+// memory but listed for a second pass.  The body is otherwise k_persistent's
 // for B = 512, written out again: routing both kernels through one inlined
 // function changes the default kernel's generated code, which is kept as it
 // was measured.
 template <int CAP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_persistent_dense(
-    sbt_params P, HitsArgs H, Work W0, int own_cap, int sortcap)
+    sbt_params P, HitsArgs H, Work W0, int own_cap, int sortcap, int defer)
 {
     constexpr int B = 512;
     constexpr uint32_t lo = 0;
@@ -98,18 +100,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
         if (e < 0) break;
         int hb, N;
         const int st = load_event<B>(P, H, e, S, &hb, &N);
-        if (tid<B>() == 0) ws_evinfo(W)[e].st = st;
-        if (st == 0) {
-            const Ev v = event_view(W, e, hb, N, lo);
-            stage_sort<B>(P, H, v, S, sortcap);
-            const bool in_lds = stage_track<B, CAP>(P, v, S, own_cap, false);
-            const int n_fin = uni(S.cnt[3]);
-            if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own(v.lo));
-            else stage_filter<B>(P, v, n_fin, v.own());
-            stage_compact<B>(v, S.scan, (int)lds_sort_head() + 4 * sortcap);
-        } else if (tid<B>() == 0) {
-            ws_evinfo(W)[e].nt = 0;
-            ws_evinfo(W)[e].nh = 0;
+        if (defer && st == 0 && !event_fits_lds<B, CAP>(S, N, own_cap)) {
+            // with defer, an event that does not fit the LDS slots is set
+            // aside for a second pass with larger slots
+            if (tid<B>() == 0) ws_deferp(W)[atomicAdd(ws_defer_countp(W), 1u)] = e;
+        } else {
+            if (tid<B>() == 0) ws_evinfo(W)[e].st = st;
+            if (st == 0) {
+                const Ev v = event_view(W, e, hb, N, lo);
+                stage_sort<B>(P, H, v, S, sortcap);
+                const bool in_lds = stage_track<B, CAP>(P, v, S, own_cap, false);
+                const int n_fin = uni(S.cnt[3]);
+                if (CAP > 0 && in_lds) stage_filter<B>(P, v, n_fin, Lay<CAP>::own(v.lo));
+                else stage_filter<B>(P, v, n_fin, v.own());
+                stage_compact<B>(v, S.scan, (int)lds_sort_head() + 4 * sortcap);
+            } else if (tid<B>() == 0) {
+                ws_evinfo(W)[e].nt = 0;
+                ws_evinfo(W)[e].nh = 0;
+            }
         }
         ev_sync<B>();
     }

@@ -86,12 +86,12 @@ class SbtTrackStates(ctypes.Structure):
 class SbtTuning(ctypes.Structure):
     _fields_ = [("threads_per_event", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("lds_window_hits", ctypes.c_int32), ("lds_owner_hits", ctypes.c_int32),
-                ("events_per_block", ctypes.c_int32)]
+                ("events_per_block", ctypes.c_int32), ("deferred_window_hits", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(threads_per_event=self.threads_per_event, blocks_per_cu=self.blocks_per_cu,
                     lds_window_hits=self.lds_window_hits, lds_owner_hits=self.lds_owner_hits,
-                    events_per_block=max(1, self.events_per_block))
+                    events_per_block=max(1, self.events_per_block), deferred_window_hits=self.deferred_window_hits)
 
 
 class SbtGraphStats(ctypes.Structure):
@@ -202,13 +202,14 @@ def make_params(module_z, **overrides) -> SbtParams:
 
 
 def make_tuning(threads_per_event=512, blocks_per_cu=2, lds_window_hits=672, lds_owner_hits=16384,
-                events_per_block=1) -> SbtTuning:
+                events_per_block=1, deferred_window_hits=0) -> SbtTuning:
     t = SbtTuning()
     t.threads_per_event = threads_per_event
     t.blocks_per_cu = blocks_per_cu
     t.lds_window_hits = lds_window_hits
     t.lds_owner_hits = lds_owner_hits
     t.events_per_block = events_per_block
+    t.deferred_window_hits = deferred_window_hits
     return t
 
 

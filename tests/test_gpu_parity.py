@@ -225,6 +225,45 @@ def test_six_waves_instance_matches_oracle(config, n, first):
     ctx.close()
 
 
+@pytest.mark.parametrize("config,n,first,deferred", [("mu1-25", 40, 0, 768), ("mu1-25", 30, 100, 1536),
+                                                     ("mu30", 4, 1, 768), ("mu30", 3, 5, 1536),
+                                                     ("mu7.6", 30, 340, 672), ("tiny", 20, 0, 768)])
+def test_two_pass_launch_matches_oracle(config, n, first, deferred):
+    """A two-pass tuning: the six-waves instance with 448-hit slots sets aside
+    the events its slots cannot hold (none, some or all of a batch), and a
+    second pass runs them with larger slots.  Direct launch, then the
+    captured graph."""
+    import torch
+    say(f"two passes {config} x{n} from {first}, second pass {deferred}-hit slots")
+    b = synth.make_batch(config, n, first=first)
+    want = oracle.reconstruct(b)
+    t = sbt.make_tuning(512, 3, 448, deferred_window_hits=deferred)
+    got = run_batched(b, t)
+    assert not got[3].any()
+    _same(got, want, f"two passes {config}")
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits, t)
+    assert ctx.get_tuning().as_dict()["deferred_window_hits"] == deferred
+    got, stats = graph_replays(ctx, sbt.DeviceBatch(b), sbt.DeviceTracks(b.n_events, b.n_hits), torch.cuda.Stream(),
+                               reps=2)
+    check_replays(got, stats, want, f"two passes {config} graph")
+    ctx.close()
+
+
+def test_two_pass_tunings_are_checked():
+    """A second pass needs the six-waves first pass (512 lanes, three or more
+    per CU, 448-hit slots) and larger slots than the first."""
+    b = synth.make_batch("tiny", 4)
+    p = sbt.make_params(b.module_z)
+    for bad in (sbt.make_tuning(256, 3, 448, deferred_window_hits=768),
+                sbt.make_tuning(512, 2, 448, deferred_window_hits=768),
+                sbt.make_tuning(512, 3, 672, deferred_window_hits=768),
+                sbt.make_tuning(512, 3, 448, deferred_window_hits=448),
+                sbt.make_tuning(512, 3, 448, deferred_window_hits=-1)):
+        with pytest.raises(sbt.SbtError):
+            sbt.Context(p, b.n_events, b.n_hits, bad).close()
+
+
 # 64-lane events several to a workgroup, one wave each: (events per
 # workgroup, slot capacity, LDS flag capacity, workgroups per CU).  Each
 # workgroup's LDS (the events' regions together) stays within 159 KiB.
@@ -595,20 +634,24 @@ def test_full_size_half_precision():
 
 
 def _expected_choice(n_events, n_hits, cus):
+    """(lanes per event, workgroups per CU, slot capacity, second-pass slots)"""
     small = n_hits <= 2500 * n_events
     large = n_hits >= 4000 * n_events
     huge = n_hits >= 9000 * n_events
     if small:
-        return (256, 5, 256) if n_events > 2 * cus else (512, 2, 448)
+        return (256, 5, 256, 0) if n_events > 2 * cus else (512, 2, 448, 0)
     if n_events <= cus or (n_events <= 2 * cus and large) or huge:
-        return (1024, 1, 1536)
+        return (1024, 1, 1536, 0)
+    if large and n_events >= 15 * cus:
+        return (512, 3, 448, 768)
     if not large and n_events >= 6 * cus:
-        return (512, 3, 448)
-    return (512, 2, 768 if large else 672)
+        return (512, 3, 448, 0)
+    return (512, 2, 768 if large else 672, 0)
 
 
 @pytest.mark.parametrize("config,n", [("mu7.6", 40), ("mu7.6", 300), ("mu1-25", 300), ("mu1-25", 1000),
-                                      ("mu7.6", 3600), ("mu30", 600), ("tiny", 100), ("tiny", 700)])
+                                      ("mu7.6", 3600), ("mu30", 600), ("tiny", 100), ("tiny", 700),
+                                      ("mu1-25", 4000)])
 def test_configuration_chosen_per_call(config, n):
     """A context created without a launch configuration chooses one per call
     from the batch's size.  Each choice, a smaller batch through the same
@@ -620,7 +663,8 @@ def test_configuration_chosen_per_call(config, n):
     p = sbt.make_params(b.module_z)
     ctx = sbt.Context(p, b.n_events, b.n_hits)
     t = ctx.get_tuning()
-    assert (t.threads_per_event, t.blocks_per_cu, t.lds_window_hits) == _expected_choice(n, b.n_hits, cus)
+    assert (t.threads_per_event, t.blocks_per_cu, t.lds_window_hits, t.deferred_window_hits) == \
+        _expected_choice(n, b.n_hits, cus)
     assert t.lds_owner_hits == 16384
     want = oracle.reconstruct(b)
     _same(ctx.reconstruct(sbt.DeviceBatch(b)).to_host(), want, f"{config} x{n} per call")
