@@ -344,6 +344,10 @@ def test_random_batches_and_launch_configurations():
         epb = int(rng.choice([1, 2, 4])) if tpe == 64 else 1
         t = sbt.make_tuning(tpe, int(rng.integers(1, 9)), int(rng.choice([0, 200, 256, 448, 672, 768, 1024, 1536])),
                             int(rng.choice([0, 1000, 4096, 16384])), events_per_block=epb)
+        if rng.integers(0, 4) == 0:
+            # two passes: the six-waves first pass, a second on larger slots
+            t = sbt.make_tuning(512, int(rng.integers(3, 5)), 448, int(rng.choice([4096, 16384])),
+                                deferred_window_hits=int(rng.choice([672, 768, 1024, 1536])))
         graph = bool(rng.integers(0, 2))
         b = synth.make_batch(config, n, first=first)
         p = sbt.make_params(b.module_z)
