@@ -241,19 +241,28 @@ int sbt_reconstruct(const sbt_params *params, const sbt_hits *hits, sbt_tracks *
 typedef struct sbt_context sbt_context;
 
 /* tuning: the launch configuration of every call, or NULL to choose it per
- * call from the batch's size on the current device: 1,024 lanes per event,
- * one workgroup per compute unit and 1,536-hit LDS slots for a batch of at
- * most one event per compute unit, or at most two of 4,000 hits or more on
- * average, or any number of 9,000 hits or more on average; otherwise 512
- * lanes, two workgroups per compute unit, and 768-hit slots for events of
- * 4,000 hits or more on average, 672-hit slots for
- * smaller ones, except that more than twelve smaller events per compute unit
- * run 256 lanes, three workgroups per compute unit, 448-hit slots
- * (lds_owner_hits 16,384 throughout).  sbt_context_set_tuning
- * and sbt_autotune install one configuration for every later call;
- * sbt_context_get_tuning reports the installed one, or without one the
- * choice for a batch of max_events events and max_hits hits.  Results never
- * depend on the configuration.                                           */
+ * call from the batch's size on the current device (lds_owner_hits 16,384
+ * throughout):
+ *   - events of 2,500 hits or fewer on average: 256 lanes, five workgroups
+ *     per compute unit and 256-hit LDS slots when there are more than two
+ *     events per compute unit, else 512 lanes, two per compute unit,
+ *     448-hit slots;
+ *   - at most one event per compute unit, or at most two of 4,000 hits or
+ *     more on average, or any number of 9,000 hits or more on average:
+ *     1,024 lanes, one workgroup per compute unit, 1,536-hit slots;
+ *   - fifteen or more events per compute unit of 4,000 hits or more on
+ *     average: two passes, 512 lanes, three workgroups per compute unit,
+ *     448-hit slots, then the events those slots cannot hold with 768-hit
+ *     slots (deferred_window_hits);
+ *   - other events of 4,000 hits or more on average: 512 lanes, two per
+ *     compute unit, 768-hit slots;
+ *   - six or more other events per compute unit: 512 lanes, three per
+ *     compute unit, 448-hit slots;
+ *   - otherwise 512 lanes, two per compute unit, 672-hit slots.
+ * sbt_context_set_tuning and sbt_autotune install one configuration for
+ * every later call; sbt_context_get_tuning reports the installed one, or
+ * without one the choice for a batch of max_events events and max_hits
+ * hits.  Results never depend on the configuration.                      */
 int sbt_context_create(const sbt_params *params, const sbt_tuning *tuning,
                        int32_t max_events, int32_t max_hits, sbt_context **out);
 void sbt_context_destroy(sbt_context *ctx);
