@@ -31,6 +31,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import re
 import os
 import subprocess
 import sys
@@ -68,23 +69,31 @@ def algorithmic_bytes(batch, eto, tho) -> int:
     return 12 * H + 4 * (E * M + 1) + 4 * (E + 1) + 4 * assigned + 4 * (T + 1) + 4 * (E + 1)
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and with whitespace collapsed, so that a
+    change of comments alone leaves the hash as it was."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the source the batched kernels are compiled from: the
+    """Hash of the code the batched kernels are compiled from: the
     persistent kernel's translation unit, the device header, the kernel
     table, the public header (argument layouts) and the event-ordering
-    kernel that runs before it (k_prepare, in sbt.hip).  Host-side code
-    elsewhere in sbt.hip does not enter, so that an unrelated change does not
-    void the committed counter summaries."""
+    kernel that runs before it (k_prepare, in sbt.hip), comments left out.
+    Host-side code elsewhere in sbt.hip does not enter, so that an unrelated
+    change does not void the committed counter summaries."""
     csrc = os.path.join(ROOT, "paper_2207_03936_amd", "csrc")
     h = hashlib.sha256()
     for f in (os.path.join(csrc, "sbt_device.h"), os.path.join(csrc, "sbt_persistent.hip"),
               os.path.join(csrc, "sbt_kernels.h"), os.path.join(ROOT, "include", "sbt.h")):
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f) as fh:
+            h.update(_code_only(fh.read()).encode())
     with open(os.path.join(csrc, "sbt.hip")) as fh:
         text = fh.read()
     start = text.index("constexpr int kOrderThreads")
-    h.update(text[start:text.index("\n}\n", start)].encode())
+    h.update(_code_only(text[start:text.index("\n}\n", start)]).encode())
     return h.hexdigest()[:16]
 
 
