@@ -607,10 +607,13 @@ def _full_batch(config, n):
     return _FULL[(config, n)]
 
 
-# full batches in the launch configurations the autotuner picks for them:
-# every event against the oracle
+# full batches in the launch configurations the autotuner and the per-call
+# rule pick for them (the two-pass one for the 10,000-event mixture): every
+# event against the oracle.  Tuples: lanes per event, workgroups per CU, slot
+# capacity[, LDS flag capacity, events per workgroup, second-pass slots].
 @pytest.mark.parametrize("config,n,tuning", [("mu1-25", 10000, (512, 2, 672)),
                                              ("mu1-25", 10000, (512, 2, 768)),
+                                             ("mu1-25", 10000, (512, 3, 448, 16384, 1, 768)),
                                              ("mu30", 2000, (1024, 1, 1536)),
                                              ("mu30", 2000, (512, 2, 672))])
 def test_full_size_all_events(config, n, tuning):
