@@ -70,3 +70,44 @@ def rounded_to_f16(batch):
     import dataclasses
     r = lambda a: np.asarray(a, np.float32).astype(np.float16).astype(np.float32)
     return dataclasses.replace(batch, x=r(batch.x), y=r(batch.y), z=r(batch.z))
+
+
+def jet_event(rng, n_tracks, phi0, sigma_phi=0.004, efficiency=0.95, dup_fraction=0.02):
+    """An event of the 26-plane geometry whose tracks all leave one vertex in
+    a narrow cone: phi ~ N(phi0, sigma_phi), eta ~ U(2, 5), so that hundreds
+    of hits of a module share one phi window (long window scans, crowded
+    pendulum lists, many competing claims).  A fraction of the hits is
+    duplicated exactly (ties on every score), and noise is spread over the
+    same cone.  Returns the per-event dict that synth.concat packs."""
+    zp = synth.PLANE_Z
+    zv = rng.normal(0.0, 20.0)
+    eta = rng.uniform(2.0, 5.0, n_tracks)
+    phi = rng.normal(phi0, sigma_phi, n_tracks)
+    theta = 2.0 * np.arctan(np.exp(-eta))
+    tx, ty = np.tan(theta) * np.cos(phi), np.tan(theta) * np.sin(phi)
+    dz = zp[None, :] - zv
+    px = tx[:, None] * dz + rng.normal(0.0, synth.SMEAR_MM, (n_tracks, zp.size))
+    py = ty[:, None] * dz + rng.normal(0.0, synth.SMEAR_MM, (n_tracks, zp.size))
+    r = np.hypot(px, py)
+    keep = (dz > 0) & (r >= synth.R_MIN) & (r <= synth.R_MAX) & (rng.random(px.shape) < efficiency)
+    tid, plane = np.nonzero(keep)
+    hx, hy = px[tid, plane], py[tid, plane]
+    n_noise = max(1, tid.size // 50)
+    nplane = rng.integers(0, zp.size, n_noise)
+    nr = rng.uniform(synth.R_MIN, synth.R_MAX, n_noise)
+    nphi = rng.normal(phi0, 3 * sigma_phi, n_noise)
+    truth = np.concatenate([tid, np.full(n_noise, -1)])
+    plane = np.concatenate([plane, nplane])
+    hx = np.concatenate([hx, nr * np.cos(nphi)])
+    hy = np.concatenate([hy, nr * np.sin(nphi)])
+    dup = rng.random(plane.size) < dup_fraction
+    truth = np.concatenate([truth, np.full(int(dup.sum()), -1)])   # a copy belongs to no particle
+    plane = np.concatenate([plane, plane[dup]])
+    hx = np.concatenate([hx, hx[dup]])
+    hy = np.concatenate([hy, hy[dup]])
+    order = np.lexsort((rng.random(plane.size), plane))
+    plane = plane[order]
+    return dict(x=hx[order].astype(np.float32), y=hy[order].astype(np.float32),
+                z=zp[plane].astype(np.float32),
+                module_counts=np.bincount(plane, minlength=zp.size).astype(np.int64),
+                truth=truth[order].astype(np.int32))

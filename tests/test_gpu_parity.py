@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from _util import event_batch, rounded_to_f16, tiny_random_event
+from _util import event_batch, jet_event, rounded_to_f16, tiny_random_event
 from paper_2207_03936_amd import sbt, synth
 
 pytestmark = pytest.mark.gpu
@@ -860,3 +860,47 @@ def test_fill_candidates_full_mu7_6_batch():
     p = sbt.make_params(b.module_z)
     _same(sbt.sbt_debug_reconstruct_fill_candidates(p, sbt.DeviceBatch(b)).to_host(), oracle.reconstruct(b),
           "fill candidates mu7.6 x1000")
+
+
+_JETS = {}
+
+
+def _jets():
+    """Seven dense-jet events (120 to 1,200 tracks in one narrow cone; the
+    busiest module holds 86 to 853 hits), with cones on the phi16 wrap at
+    angle 0 and on the +-pi branch of the angle, exactly duplicated hits and
+    noise in the cone, and the oracle's tracks for them (computed once)."""
+    if not _JETS:
+        rng = np.random.default_rng(11)
+        specs = ((300, 0.0, 0.004), (300, np.pi, 0.004), (120, 1.0, 0.004), (700, -np.pi / 2, 0.004),
+                 (700, 0.0, 0.004), (1200, np.pi, 0.004), (1200, 0.0, 0.001))
+        b = synth.concat([jet_event(rng, n, phi0, sig) for n, phi0, sig in specs], synth.PLANE_Z)
+        _JETS["b"] = b
+        _JETS["want"] = oracle.reconstruct(b)
+        _JETS["b16"] = rounded_to_f16(b)
+        _JETS["want16"] = oracle.reconstruct(_JETS["b16"])
+    return _JETS
+
+
+# dense jets in every form: hundreds of hits per phi window make long window
+# scans, crowded pendulum lists and many competing claims, and the busiest
+# modules cross every LDS slot capacity (memory form included)
+@pytest.mark.parametrize("form", ["plain", "per-call", "512x2x672", "512x2x0", "64x4x0", "256x3x448",
+                                  "1024x1x1536", "two-pass", "f16"])
+def test_dense_jets_match_oracle(form):
+    J = _jets()
+    say(f"dense jets, {form}")
+    if form == "plain":
+        got, want = run_plain(J["b"]), J["want"]
+    elif form == "per-call":
+        got, want = run_batched(J["b"]), J["want"]
+    elif form == "two-pass":
+        got, want = run_batched(J["b"], sbt.make_tuning(512, 3, 448, deferred_window_hits=1536)), J["want"]
+    elif form == "f16":
+        got, want = run_batched_f16(J["b16"], sbt.make_tuning(512, 2, 672)), J["want16"]
+    else:
+        tpe, bpc, cap = (int(v) for v in form.split("x"))
+        got, want = run_batched(J["b"], sbt.make_tuning(tpe, bpc, cap)), J["want"]
+    assert not got[3].any()
+    _same(got, want, f"dense jets {form}")
+    _invariants(J["b"], got)
