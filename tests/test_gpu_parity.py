@@ -904,3 +904,47 @@ def test_dense_jets_match_oracle(form):
     assert not got[3].any()
     _same(got, want, f"dense jets {form}")
     _invariants(J["b"], got)
+
+
+_PARAM_BATCH = {}
+
+
+def _param_batch():
+    """Eight mu = 7.6 events, one mu = 30 event and two module-pair events."""
+    if "b" not in _PARAM_BATCH:
+        evs = ([synth._slice(synth.make_batch("mu7.6", 8, first=500), e) for e in range(8)]
+               + [synth._slice(synth.make_batch("mu30", 1, first=7), 0)]
+               + [synth._slice(synth.make_batch("pairs7.6", 2), e) for e in range(2)])
+        _PARAM_BATCH["b"] = synth.concat(evs, synth.PLANE_Z)
+    return _PARAM_BATCH["b"]
+
+
+# method parameters away from the defaults on full-size events: doublet
+# candidates K = 8 and 16 (the K partners of a middle hit on K adjacent
+# lanes), 3 and 64 (all K on one lane), 1 and 2; windows of the whole circle
+# and of one phi16 unit; forward traversal; looser thresholds
+PARAM_SETS = {
+    "K8": dict(max_doublet_candidates=8),
+    "K16": dict(max_doublet_candidates=16),
+    "K3": dict(max_doublet_candidates=3),
+    "K1-nomiss": dict(max_doublet_candidates=1, max_consecutive_misses=0),
+    "K2-forward": dict(max_doublet_candidates=2, reverse=0),
+    "K64-fullcircle": dict(max_doublet_candidates=64, phi_window_seeding=32767, phi_window_forwarding=32767),
+    "W0": dict(phi_window_seeding=0, phi_window_forwarding=0),
+    "loose": dict(max_scatter_seeding=1.0, max_scatter_forwarding=1.0, max_tracklet_chi2=1.0,
+                  max_consecutive_misses=2),
+}
+
+
+@pytest.mark.parametrize("name", list(PARAM_SETS))
+def test_parameters_at_scale(name):
+    kw = PARAM_SETS[name]
+    b = _param_batch()
+    say(f"parameters {name} on {b.n_events} full-size events")
+    want = oracle.reconstruct(b, **kw)
+    _same(run_plain(b, **kw), want, f"plain {name}")
+    for t in (None, sbt.make_tuning(512, 2, 672), sbt.make_tuning(256, 3, 448), sbt.make_tuning(1024, 1, 1536),
+              sbt.make_tuning(512, 2, 0), sbt.make_tuning(64, 8, 256, 4096, 2)):
+        got = run_batched(b, t, **kw)
+        assert not got[3].any()
+        _same(got, want, f"batched {name} {None if t is None else t.as_dict()}")
