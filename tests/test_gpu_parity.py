@@ -944,7 +944,29 @@ def test_parameters_at_scale(name):
     want = oracle.reconstruct(b, **kw)
     _same(run_plain(b, **kw), want, f"plain {name}")
     for t in (None, sbt.make_tuning(512, 2, 672), sbt.make_tuning(256, 3, 448), sbt.make_tuning(1024, 1, 1536),
-              sbt.make_tuning(512, 2, 0), sbt.make_tuning(64, 8, 256, 4096, 2)):
+              sbt.make_tuning(512, 2, 0), sbt.make_tuning(64, 8, 256, 4096, 2),
+              sbt.make_tuning(512, 3, 448), sbt.make_tuning(512, 3, 448, deferred_window_hits=768)):
         got = run_batched(b, t, **kw)
         assert not got[3].any()
         _same(got, want, f"batched {name} {None if t is None else t.as_dict()}")
+
+
+def test_thirty_thousand_small_events():
+    """30,000 single-vertex events (12.9 M hits) in one call: the event
+    ordering, the scan over events and the CSR write loop over many batches
+    of events; the per-call configuration (small-event branch), the plain
+    form, 64-lane events four to a workgroup, and the captured graph."""
+    import torch
+    say("30,000 tiny events")
+    b = synth.make_batch("tiny", 30000)
+    want = oracle.reconstruct(b)
+    say(f"  oracle done, {int(want[0][-1])} tracks")
+    _same(run_batched(b), want, "30k per-call")
+    _same(run_plain(b), want, "30k plain")
+    _same(run_batched(b, sbt.make_tuning(64, 2, 256, 4096, 4)), want, "30k 64-lane x4")
+    p = sbt.make_params(b.module_z)
+    ctx = sbt.Context(p, b.n_events, b.n_hits)
+    got, stats = graph_replays(ctx, sbt.DeviceBatch(b), sbt.DeviceTracks(b.n_events, b.n_hits), torch.cuda.Stream(),
+                               reps=2)
+    check_replays(got, stats, want, "30k graph")
+    ctx.close()
