@@ -240,6 +240,10 @@ __device__ __forceinline__ void ev_lds_sync()
 // every module step, so values derived from them are recomputed per step
 // instead of being hoisted out of the event and step loops, where dozens of
 // them would stay live in scalar registers (and spill) for the whole kernel.
+// The "+s" operand must reach the asm in a scalar register: where a change
+// elsewhere in a kernel leaves the compiler holding it in a vector register,
+// compilation stops with an illegal VGPR-to-SGPR copy (a readfirstlane on
+// the input resolves it, at the price of a different register allocation).
 template <class T>
 __device__ __forceinline__ T opq(T v)
 {
