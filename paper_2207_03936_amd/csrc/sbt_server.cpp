@@ -313,13 +313,28 @@ std::shared_ptr<ResultBlock> new_block(const SlotLayout &L)
     return b;
 }
 
-// a block no slot or result refers to any more, else a new one
-std::shared_ptr<ResultBlock> free_block(sbt_server *srv, const SlotLayout &L)
+// Result blocks a server may hold: one per slot on the device, and as many
+// again plus two for completed results not yet returned or last returned.
+// Past that, launches wait until the caller's polls release blocks.
+size_t max_blocks(const sbt_server *srv) { return 2 * srv->slots.size() + 2; }
+
+// A launch that has to wait for a result block (internal, never returned).
+constexpr int kWaitForBlock = 1;
+
+// a block no slot or result refers to any more, else a new one; nullptr with
+// *rc = kWaitForBlock at the limit, SBT_ERR_NOMEM when allocation fails
+std::shared_ptr<ResultBlock> free_block(sbt_server *srv, const SlotLayout &L, int *rc)
 {
+    *rc = SBT_OK;
     for (auto &b : srv->blocks)
         if (b.use_count() == 1) return b;
+    if (srv->blocks.size() >= max_blocks(srv)) {
+        *rc = kWaitForBlock;
+        return nullptr;
+    }
     std::shared_ptr<ResultBlock> b = new_block(L);
     if (b) srv->blocks.push_back(b);
+    else *rc = SBT_ERR_NOMEM;
     return b;
 }
 
@@ -371,8 +386,9 @@ int launch(sbt_server *srv, Slot &s)
     const size_t E = (size_t)s.n_events, H = (size_t)s.n_hits;
     const size_t stride = xyz_stride(H);
     hipStream_t st = s.stream;
-    std::shared_ptr<ResultBlock> block = free_block(srv, L);
-    if (!block) return SBT_ERR_NOMEM;
+    int brc;
+    std::shared_ptr<ResultBlock> block = free_block(srv, L, &brc);
+    if (!block) return brc;
     // hits into the pinned staging, packed for this launch, in parallel over
     // events: x, y, z arrays, or binary16 records
     const bool f16 = srv->cfg.coords_f16 != 0;
@@ -485,6 +501,7 @@ int step(sbt_server *srv)
         QueuedEvent &q = srv->queue.front();
         if (s.n_events + 1 > srv->cfg.slot_events || s.n_hits + q.n > srv->cfg.slot_hits) {
             int rc = launch(srv, s);        // full: launch it and open another
+            if (rc == kWaitForBlock) break;   // events wait on the host
             if (rc) return rc;
             ++in_flight;
             srv->open_slot = -1;
@@ -498,6 +515,7 @@ int step(sbt_server *srv)
         Slot &s = srv->slots[(size_t)srv->open_slot];
         if (s.n_events > 0 && (in_flight == 0 || t - s.t_oldest >= (double)srv->cfg.max_wait_us)) {
             int rc = launch(srv, s);
+            if (rc == kWaitForBlock) return SBT_OK;   // launched once a poll releases a block
             if (rc) return rc;
             srv->open_slot = -1;
         }
@@ -567,7 +585,7 @@ int sbt_server_create(const sbt_params *params, const sbt_tuning *tuning, const 
         }
     }
     // one result block per slot and one for the results last returned; more
-    // are added while callers hold results longer
+    // (up to max_blocks) are added while callers leave results unreturned
     for (int i = 0; i <= c.n_slots; ++i) {
         std::shared_ptr<ResultBlock> b = new_block(L);
         if (!b) {
@@ -661,7 +679,10 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
         if (n < 0) return SBT_ERR_INVALID_ARG;
         if (n > SBT_MAX_EVENT_HITS) return SBT_ERR_EVENT_TOO_LARGE;
     }
-    std::vector<sbt_server_result> res(512);
+    // room for every result the slots can complete at once, so that each
+    // poll returns all of them and their result blocks are released promptly
+    std::vector<sbt_server_result> res(
+        std::max<size_t>(512, srv->slots.size() * (size_t)srv->cfg.slot_events));
     const double t0 = now_us();
     int32_t next = 0, done = 0;
     while (done < n_arrivals) {
@@ -691,6 +712,14 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
         }
     }
     *wall_us = now_us() - t0;
+    return SBT_OK;
+}
+
+int sbt_server_result_blocks(const sbt_server *srv, int32_t *n_blocks, int32_t *limit)
+{
+    if (!srv) return SBT_ERR_INVALID_ARG;
+    if (n_blocks) *n_blocks = (int32_t)srv->blocks.size();
+    if (limit) *limit = (int32_t)max_blocks(srv);
     return SBT_OK;
 }
 

@@ -148,6 +148,7 @@ PROTOTYPES = {
                                          _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float)]),
     "sbt_server_poll": (ctypes.c_int, [_VP, _P(SbtServerResult), ctypes.c_int32, ctypes.c_int32]),
     "sbt_server_pending": (ctypes.c_int, [_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "sbt_server_result_blocks": (ctypes.c_int, [_VP, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
     "sbt_server_replay": (ctypes.c_int, [_VP, ctypes.c_int32, _P(ctypes.c_double), _P(ctypes.c_int32),
                                          ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
                                          _P(ctypes.c_float), _P(ctypes.c_float), _P(ctypes.c_float),
@@ -643,10 +644,12 @@ class Server:
                                        mo.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                        x.ctypes.data_as(f), y.ctypes.data_as(f), z.ctypes.data_as(f))
 
-    def poll(self, wait_us: int = 0):
+    def poll(self, wait_us: int = 0, max_results: Optional[int] = None):
         """List of (request_id, status, track_hit_offsets, track_hits,
-        t_submit_us, t_done_us) for the events completed so far."""
-        n = lib().sbt_server_poll(self.handle, self._res, len(self._res), int(wait_us))
+        t_submit_us, t_done_us) for the events completed so far (at most
+        max_results of them)."""
+        cap = len(self._res) if max_results is None else max(0, min(int(max_results), len(self._res)))
+        n = lib().sbt_server_poll(self.handle, self._res, cap, int(wait_us))
         if n < 0:
             raise SbtError(n, "sbt_server_poll")
         out = []
@@ -689,6 +692,13 @@ class Server:
         q, f = ctypes.c_int32(0), ctypes.c_int32(0)
         _check(lib().sbt_server_pending(self.handle, ctypes.byref(q), ctypes.byref(f)), "sbt_server_pending")
         return int(q.value), int(f.value)
+
+    def result_blocks(self):
+        """(result blocks held, most the server will hold)."""
+        n, cap = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().sbt_server_result_blocks(self.handle, ctypes.byref(n), ctypes.byref(cap)),
+               "sbt_server_result_blocks")
+        return int(n.value), int(cap.value)
 
 
 def sbt_now_us() -> float:

@@ -203,3 +203,35 @@ def test_replay_refused_while_events_are_pending():
     lat, nt, wall = srv.replay(pool, np.zeros(3), np.array([0, 1, 2]))
     assert np.array_equal(nt, np.diff(oracle.reconstruct(pool)[0])[[0, 1, 2]])
     srv.close()
+
+
+def test_slow_consumer_holds_a_bounded_number_of_result_blocks():
+    """A caller that takes one result per poll leaves completed results
+    unreturned.  The server then holds at most 2 * n_slots + 2 pinned result
+    blocks: further launches wait, their events stay queued, until polls have
+    returned enough results.  Every event still comes back, equal to the
+    oracle's."""
+    say("serving with a slow consumer")
+    b = synth.make_batch("tiny", 300)
+    want = _oracle_tracks(b)
+    params = sbt.make_params(b.module_z)
+    srv = sbt.Server(params, device_budget_bytes=1 << 30, n_slots=2, slot_events=8, slot_hits=1 << 16,
+                     max_wait_us=0)
+    got, seen = {}, []
+    e = 0
+    t_end = time.time() + 120.0
+    while len(got) < b.n_events:
+        while e < b.n_events and srv.submit(e, *_event(b, e)) == 0:
+            e += 1
+        for (rid, st, tho, th, ts, td) in srv.poll(0, max_results=1):
+            got[rid] = (st, tho, th)
+        seen.append(srv.result_blocks())
+        assert time.time() < t_end, f"serving stalled with {len(got)}/{b.n_events} results"
+    srv.close()
+    limit = seen[0][1]
+    assert limit == 2 * 2 + 2
+    assert max(n for n, _ in seen) == limit   # the limit was reached and held
+    for i in range(b.n_events):
+        st, tho, th = got[i]
+        assert st == 0
+        assert np.array_equal(tho, want[i][0]) and np.array_equal(th, want[i][1]), f"event {i}"
