@@ -58,6 +58,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def guarded(name, fn, errors):
+    """One leg run after the headline: an error of the kinds listed is
+    reported in that leg's place in the line instead of ending the run."""
+    try:
+        return fn()
+    except errors as e:
+        log(f"{name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def algorithmic_bytes(batch, eto, tho) -> int:
     """Bytes the method must move for a batch: hits in (3 x 4 B), module and
     event offsets in (4 B each), track hit ids and track offsets out (4 B
@@ -764,10 +774,12 @@ def main():
         result["sequence"] = seq_leg
     del ws
     ctx.close()
+    # the legs below report a library or runtime error in their place
+    errors = (sbt.SbtError, RuntimeError)
     for name, b in extra.items():
-        result[name] = workload_leg(torch, sbt, b, name, max(5, args.steps // 5), 2, gstream,
-                                    50 if name == "mu1-25" else 20)
-        log(f"{name}: {result[name]['events_per_s']} events/s")
+        result[name] = guarded(name, lambda: workload_leg(torch, sbt, b, name, max(5, args.steps // 5), 2, gstream,
+                                                          50 if name == "mu1-25" else 20), errors)
+        log(f"{name}: {result[name].get('events_per_s')} events/s")
     extra.clear()
     if not args.no_serve:
         # algorithmic bytes per event of the serving pool, from one batched call over it
@@ -776,17 +788,18 @@ def main():
         pgot = pctx.reconstruct(sbt.DeviceBatch(pool)).to_host()
         pctx.close()
         per_event = algorithmic_bytes(pool, pgot[0], pgot[1]) / pool.n_events
-        result["serving"] = serving_leg(params, args.serve_seconds, bytes_per_event=per_event)
-        result["p99_event_latency_ms"] = result["serving"]["p99_ms"]
-        log(f"serving: p99 {result['serving']['p99_ms']} ms")
+        result["serving"] = guarded("serving", lambda: serving_leg(params, args.serve_seconds,
+                                                                   bytes_per_event=per_event), errors)
+        result["p99_event_latency_ms"] = result["serving"].get("p99_ms")
+        log(f"serving: p99 {result['serving'].get('p99_ms')} ms")
         # the same server closer to its burst saturation
-        result["serving_80pct"] = serving_leg(params, args.serve_seconds, fraction=0.8,
-                                              bytes_per_event=per_event)
-        log(f"serving at 80 %: p99 {result['serving_80pct']['p99_ms']} ms")
+        result["serving_80pct"] = guarded("serving_80pct", lambda: serving_leg(
+            params, args.serve_seconds, fraction=0.8, bytes_per_event=per_event), errors)
+        log(f"serving at 80 %: p99 {result['serving_80pct'].get('p99_ms')} ms")
         # the same with hits sent to the device as binary16 (results are those
         # of the rounded hits): 80 % of its own burst saturation
-        result["serving_f16"] = serving_leg(params, args.serve_seconds, fraction=0.8, coords_f16=True,
-                                            bytes_per_event=per_event)
+        result["serving_f16"] = guarded("serving_f16", lambda: serving_leg(
+            params, args.serve_seconds, fraction=0.8, coords_f16=True, bytes_per_event=per_event), errors)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(batch, got, args.workload)
         result["cpu_baseline"].update(host_cpu())

@@ -69,3 +69,19 @@ def test_committed_summaries_name_their_tuning():
             d = json.load(f)
         assert set(bench.TUNING_KEYS) <= set(d["tuning"]), name
         assert "kernel" in d and "commands" in d, name
+
+
+def test_guarded_leg_reports_listed_errors_only():
+    """A leg after the headline reports a listed error in its place; any
+    other error still ends the run."""
+    import pytest
+    assert bench.guarded("ok", lambda: {"v": 1}, (RuntimeError,)) == {"v": 1}
+
+    def fail():
+        raise RuntimeError("no memory")
+    assert bench.guarded("bad", fail, (RuntimeError,)) == {"error": "RuntimeError: no memory"}
+
+    def other():
+        raise KeyError("x")
+    with pytest.raises(KeyError):
+        bench.guarded("other", other, (RuntimeError,))
