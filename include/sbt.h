@@ -472,7 +472,7 @@ int sbt_server_submit(sbt_server *srv, int64_t request_id, int32_t n_hits,
  * wait_us > 0 it blocks up to that long for at least one completion.
  * Each launch writes its results into a pinned host result block, which is
  * reused once no slot and no completed result refers to it.  The server
- * holds at most 2 * n_slots + 2 blocks: while completed results stay
+ * holds at most 3 * n_slots + 2 blocks: while completed results stay
  * unreturned (polls with a small max_results), further launches wait, and
  * their events stay queued, until polls have returned enough results.     */
 int sbt_server_poll(sbt_server *srv, sbt_server_result *results, int32_t max_results,
@@ -500,7 +500,7 @@ int sbt_server_replay(sbt_server *srv, int32_t n_arrivals, const double *arrival
 int sbt_server_pending(const sbt_server *srv, int32_t *queued, int32_t *in_flight);
 
 /* Result blocks the server holds (each the pinned host memory for one
- * slot's results) and the most it will hold (2 * n_slots + 2).  Either
+ * slot's results) and the most it will hold (3 * n_slots + 2).  Either
  * pointer may be NULL.  SBT_OK, or SBT_ERR_INVALID_ARG for a NULL server. */
 int sbt_server_result_blocks(const sbt_server *srv, int32_t *n_blocks, int32_t *limit);
 

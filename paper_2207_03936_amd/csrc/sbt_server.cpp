@@ -313,10 +313,12 @@ std::shared_ptr<ResultBlock> new_block(const SlotLayout &L)
     return b;
 }
 
-// Result blocks a server may hold: one per slot on the device, and as many
-// again plus two for completed results not yet returned or last returned.
-// Past that, launches wait until the caller's polls release blocks.
-size_t max_blocks(const sbt_server *srv) { return 2 * srv->slots.size() + 2; }
+// Result blocks a server may hold: one per slot on the device, one per slot
+// for results completed since the last poll and one per slot for the results
+// that poll returned (valid until the next), and two more.  Past that, which
+// only a caller leaving completed results unreturned reaches, launches wait
+// until its polls release blocks.
+size_t max_blocks(const sbt_server *srv) { return 3 * srv->slots.size() + 2; }
 
 // A launch that has to wait for a result block (internal, never returned).
 constexpr int kWaitForBlock = 1;

@@ -207,7 +207,7 @@ def test_replay_refused_while_events_are_pending():
 
 def test_slow_consumer_holds_a_bounded_number_of_result_blocks():
     """A caller that takes one result per poll leaves completed results
-    unreturned.  The server then holds at most 2 * n_slots + 2 pinned result
+    unreturned.  The server then holds at most 3 * n_slots + 2 pinned result
     blocks: further launches wait, their events stay queued, until polls have
     returned enough results.  Every event still comes back, equal to the
     oracle's."""
@@ -229,7 +229,7 @@ def test_slow_consumer_holds_a_bounded_number_of_result_blocks():
         assert time.time() < t_end, f"serving stalled with {len(got)}/{b.n_events} results"
     srv.close()
     limit = seen[0][1]
-    assert limit == 2 * 2 + 2
+    assert limit == 3 * 2 + 2
     assert max(n for n, _ in seen) == limit   # the limit was reached and held
     for i in range(b.n_events):
         st, tho, th = got[i]
