@@ -88,19 +88,33 @@ def _code_only(text: str) -> str:
     return " ".join(text.split())
 
 
+def _layouts(text: str) -> str:
+    """The constants and struct layouts of a header, comments left out:
+    what device code compiles against (function declarations generate no
+    code)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    parts = re.findall(r"^[ \t]*#define[^\n]*", text, flags=re.M)
+    parts += re.findall(r"typedef\s+struct\b.*?\}\s*\w+\s*;", text, flags=re.S)
+    return " ".join(" ".join(parts).split())
+
+
 def kernel_source_hash() -> str:
     """Hash of the code the batched kernels are compiled from: the
     persistent kernel's translation unit, the device header, the kernel
-    table, the public header (argument layouts) and the event-ordering
-    kernel that runs before it (k_prepare, in sbt.hip), comments left out.
+    table, the public header's constants and argument layouts, and the
+    event-ordering kernel that runs before it (k_prepare, in sbt.hip),
+    comments left out.
     Host-side code elsewhere in sbt.hip does not enter, so that an unrelated
     change does not void the committed counter summaries."""
     csrc = os.path.join(ROOT, "paper_2207_03936_amd", "csrc")
     h = hashlib.sha256()
     for f in (os.path.join(csrc, "sbt_device.h"), os.path.join(csrc, "sbt_persistent.hip"),
-              os.path.join(csrc, "sbt_kernels.h"), os.path.join(ROOT, "include", "sbt.h")):
+              os.path.join(csrc, "sbt_kernels.h")):
         with open(f) as fh:
             h.update(_code_only(fh.read()).encode())
+    with open(os.path.join(ROOT, "include", "sbt.h")) as fh:
+        h.update(_layouts(fh.read()).encode())
     with open(os.path.join(csrc, "sbt.hip")) as fh:
         text = fh.read()
     start = text.index("constexpr int kOrderThreads")
