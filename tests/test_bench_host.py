@@ -85,3 +85,13 @@ def test_guarded_leg_reports_listed_errors_only():
         raise KeyError("x")
     with pytest.raises(KeyError):
         bench.guarded("other", other, (RuntimeError,))
+
+
+def test_committed_summaries_describe_the_committed_kernels():
+    """The committed counter summaries were taken on the kernel source as it
+    is (comments aside), so the benchmark line carries their traffic and
+    instruction counts; a kernel change needs them taken again."""
+    h = bench.kernel_source_hash()
+    for name in ("k_persistent_mu7.6_x1000_traffic.json", "k_persistent_mu7.6_x1000_sq.json"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            assert json.load(f)["kernel_source_hash"] == h, name
