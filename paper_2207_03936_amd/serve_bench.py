@@ -52,13 +52,16 @@ def run_rate(srv, pool, rate, seconds, seed=123, max_events=2_000_000):
                 max_ms=round(float(lat_ms.max()), 4), n_tracks=int(nt.sum()))
 
 
-def saturation(srv, pool, max_events):
+def saturation(srv, pool, max_events, repeats=3):
     """Saturated throughput: every arrival at time zero.  A discarded first
     pass of up to 20,000 events warms the server (result blocks, staging
     threads, the kernels' first launches), which otherwise shows as a lower
-    first figure."""
+    first figure.  A burst lasts a fraction of a second, so it is repeated
+    and the run of median throughput is returned."""
     run_rate(srv, pool, 0, 0, max_events=min(20_000, max_events))
-    return run_rate(srv, pool, 0, 0, max_events=max_events)
+    runs = sorted((run_rate(srv, pool, 0, 0, seed=123 + i, max_events=max_events) for i in range(repeats)),
+                  key=lambda r: r["sustained_events_per_s"])
+    return runs[len(runs) // 2]
 
 
 def main(argv=None):
