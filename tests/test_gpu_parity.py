@@ -380,7 +380,7 @@ def test_random_tiny_events_and_parameters():
         b = synth.concat([dict(x=x, y=y, z=z, module_counts=np.diff(mo).astype(np.int64),
                                truth=np.full(len(x), -1, np.int32)) for (x, y, z, mo, mz) in evs], evs[0][4])
         kw = dict(reverse=int(rng.integers(0, 2)),
-                  max_doublet_candidates=int(rng.choice([1, 2, 4, 64])),
+                  max_doublet_candidates=int(rng.choice([1, 2, 3, 4, 8, 16, 64])),
                   phi_window_seeding=int(rng.choice([20, 416, 32767])),
                   phi_window_forwarding=int(rng.choice([20, 416, 32767])),
                   max_scatter_seeding=float(rng.choice([0.05, 1.0, 20.0])),
@@ -845,7 +845,7 @@ def test_fill_candidates_pass_random_parameters():
         evs = [tiny_random_event(rng, M=6, jitter_z=bool(i % 2)) for _ in range(8)]
         b = synth.concat([dict(x=x, y=y, z=z, module_counts=np.diff(mo).astype(np.int64),
                                truth=np.full(len(x), -1, np.int32)) for (x, y, z, mo, mz) in evs], evs[0][4])
-        kw = dict(reverse=int(rng.integers(0, 2)), max_doublet_candidates=int(rng.choice([1, 2, 4, 64])),
+        kw = dict(reverse=int(rng.integers(0, 2)), max_doublet_candidates=int(rng.choice([1, 2, 3, 4, 8, 16, 64])),
                   phi_window_seeding=int(rng.choice([20, 416, 32767])),
                   max_consecutive_misses=int(rng.choice([0, 1, 2])))
         say(f"fill candidates random batch {i} {kw}")
