@@ -740,21 +740,26 @@ def main():
     tctx.close()
     del tout
     log(f"autotune picked {autotune['tuning']}: {autotune['ms_per_step']} ms")
+    # the legs from here on report a library or runtime error in their place
+    errors = (sbt.SbtError, RuntimeError)
     if not args.no_e2e:
-        e2e = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(5, min(args.steps, 20)), False)
+        e2e = guarded("end_to_end", lambda: end_to_end(torch, sbt, params, ctx.get_tuning(), batch,
+                                                       max(5, min(args.steps, 20)), False), errors)
         pipe_streams = extra_streams
-        e2e_p = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
-                           streams=pipe_streams)
+        e2e_p = guarded("end_to_end_pipelined", lambda: end_to_end(
+            torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True,
+            streams=pipe_streams), errors)
     # half-precision array-of-structures input (the paper's hit-storage optimisation)
     dev16 = sbt.DeviceBatchF16(batch)
     out16 = sbt.DeviceTracks(E, H)
     sec_f16 = timed(lambda: ctx.reconstruct_f16(dev16, out16, gstream), args.steps, args.warmup)
     got16 = out16.to_host()
     if not args.no_e2e:
-        e2e_f16 = end_to_end(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
-                             streams=pipe_streams)
-        seq_leg = sequence_leg(torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)),
-                               pipe_streams)
+        e2e_f16 = guarded("end_to_end_f16", lambda: end_to_end(
+            torch, sbt, params, ctx.get_tuning(), batch, max(10, min(args.steps, 40)), True, True,
+            streams=pipe_streams), errors)
+        seq_leg = guarded("sequence", lambda: sequence_leg(torch, sbt, params, ctx.get_tuning(), batch,
+                                                           max(10, min(args.steps, 40)), pipe_streams), errors)
     del dev16, out16
     log("binary16, end-to-end and sequence legs done")
 
@@ -788,8 +793,6 @@ def main():
         result["sequence"] = seq_leg
     del ws
     ctx.close()
-    # the legs below report a library or runtime error in their place
-    errors = (sbt.SbtError, RuntimeError)
     for name, b in extra.items():
         result[name] = guarded(name, lambda: workload_leg(torch, sbt, b, name, max(5, args.steps // 5), 2, gstream,
                                                           50 if name == "mu1-25" else 20), errors)
